@@ -1,0 +1,358 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix,
+independently of the oracle's own formulas (CPU only).
+
+* Kernels: symmetry, incompressibility and harmonicity by finite differences,
+  and the Stokes equation -mu Lap u + grad p = 0 with the paper's pressure
+  kernel Pi = 2 d / r^3 (Section 2.2), which ties the Stokeslet's
+  normalisation to the pressure's.
+* One sphere (textbook closed forms, not printed in the paper): translational
+  mobility 1/(6 pi mu a), rotational 1/(8 pi mu a^3), capacitance 4 pi a.
+* P = 1: the preconditioned system is the identity and the recovered strengths
+  equal the dense least-squares solution of the tall system.
+* Small clusters: the matvec equals the square matrix of eq. (2esysprec)
+  assembled from dense blocks and an explicit pseudo-inverse; GMRES equals a
+  dense LU solve; the per-shape rotated factor equals a per-body factor.
+* Invariants (Propositions 1-2): exact net charge / force / torque of the
+  strengths; lambda_0 is the minimum-norm solution of K_N^T mu = [f; t];
+  constant potential / rigid motion at the collocation nodes of one body.
+* Symmetry and positivity of the mobility matrix, translation invariance,
+  rotation covariance, two-body far-field asymptotics.
+* Adjoint: dot-product identity and central finite differences of the loss.
+* A planted mistake in the oracle makes a pin fail.
+"""
+import numpy as np
+import pytest
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import rel_inf
+
+RNG = np.random.default_rng(123)
+
+
+# ---------------------------------------------------------------------------
+# kernels
+# ---------------------------------------------------------------------------
+
+def test_stokeslet_symmetric_and_even():
+    d = RNG.standard_normal((20, 3))
+    G = O.stokeslet(d)
+    assert np.allclose(G, np.swapaxes(G, 1, 2), atol=0, rtol=1e-15)
+    assert np.allclose(G, O.stokeslet(-d), atol=0, rtol=1e-15)
+
+
+def _fd_grad(f, x, h=1e-4):
+    g = np.zeros(3)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        g[a] = (f(x + e) - f(x - e)) / (2 * h)
+    return g
+
+
+def _fd_lap(f, x, h=1e-3):
+    s = 0.0
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        s += (f(x + e) - 2 * f(x) + f(x - e)) / (h * h)
+    return s
+
+
+def test_stokeslet_divergence_free_and_stokes_equation():
+    mu = 1.0
+    y = np.array([0.1, -0.2, 0.3])
+    f = np.array([0.7, -1.1, 0.4])
+    u = lambda x: O.stokeslet(x - y, mu) @ f
+    # pressure of a Stokeslet with the paper's kernel: p = Pi . f / (8 pi), Pi = 2 d / r^3
+    p = lambda x: (2 * (x - y) / np.linalg.norm(x - y) ** 3) @ f / (8 * np.pi)
+    for x in RNG.standard_normal((5, 3)) * 2 + 2.0:
+        div = sum(_fd_grad(lambda z: u(z)[a], x)[a] for a in range(3))
+        assert abs(div) < 1e-7
+        lap_u = np.array([_fd_lap(lambda z: u(z)[a], x) for a in range(3)])
+        res = -mu * lap_u + _fd_grad(p, x)
+        assert np.abs(res).max() < 1e-4 * np.abs(lap_u).max()
+
+
+def test_laplace_kernel_harmonic_and_unit_flux():
+    y = np.zeros(3)
+    G = lambda x: O.laplace_G(x - y)
+    for x in RNG.standard_normal((5, 3)) + 1.5:
+        assert abs(_fd_lap(G, x)) < 1e-5 * abs(G(x))
+    # -Lap G = delta: flux of -grad G through a sphere is 1
+    pts = W.fibonacci_sphere(4000, 0.5)
+    flux = np.mean([-_fd_grad(G, q) @ (q / 0.5) for q in pts]) * 4 * np.pi * 0.25
+    assert abs(flux - 1.0) < 1e-6
+
+
+def test_pair_sums_match_dense_blocks():
+    wl = W.small_cluster(3, W.STOKES, 20, 40, seed=3)
+    pr = O.Problem.from_workload(wl)
+    s = RNG.standard_normal(pr.n_lambda)
+    dense = np.zeros(pr.n_gamma)
+    for k, bk in enumerate(pr.bodies):
+        for kp, bkp in enumerate(pr.bodies):
+            if k != kp:
+                dense[pr.trg_off[k]:pr.trg_off[k + 1]] += O.S_block(1, bk.X, bkp.Y) @ pr.sblock(s, kp)
+    assert rel_inf(pr._p2p(s, True), dense) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# one body
+# ---------------------------------------------------------------------------
+
+def test_single_sphere_stokes_closed_form():
+    wl = W.single_sphere(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    F = wl.net[0][0]
+    U = pr.solve(wl.net[0], tol=1e-13)["out"][0]
+    assert rel_inf(U[:3], F[:3] / (6 * np.pi)) < 1e-6
+    assert rel_inf(U[3:], F[3:] / (8 * np.pi)) < 1e-6
+
+
+def test_single_sphere_capacitance_and_convergence():
+    errs = []
+    for n in (100, 300):
+        wl = W.single_sphere(W.LAPLACE, n_src=n, n_trg=2 * n)
+        phi = O.Problem.from_workload(wl).solve(np.ones(1), tol=1e-13)["out"][0]
+        errs.append(abs(phi * 4 * np.pi - 1.0))
+    assert errs[1] < 1e-7
+    assert errs[1] < errs[0]
+    # a sphere of radius 2 has capacitance 8 pi
+    wl = W.single_sphere(W.LAPLACE, radius=2.0, proxy_radius=1.4)
+    phi = O.Problem.from_workload(wl).solve(np.ones(1), tol=1e-13)["out"][0]
+    assert abs(phi * 8 * np.pi - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_single_body_matches_dense_least_squares(kind):
+    wl = W.small_cluster(1, kind, 60, 130, seed=4)
+    pr = O.Problem.from_workload(wl, per_body=True)
+    g = W.random_vector(pr.n_gamma, 5)
+    assert rel_inf(pr.matvec(g), g) < 1e-15                   # P = 1: A = I
+    sol = pr.solve(wl.net[0], tol=1e-13)
+    assert rel_inf(sol["gamma"], sol["b"]) < 1e-13
+    lam_ls = np.linalg.lstsq(pr.S_L(0), sol["b"], rcond=None)[0]
+    assert rel_inf(sol["lam"], lam_ls) < 1e-9
+
+
+def test_collocation_residual_one_body():
+    """Proposition 2 on one body: the flow of sigma is the rigid motion K_M U at
+    the collocation nodes up to the tall system's least-squares residual."""
+    wl = W.single_sphere(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    sol = pr.solve(wl.net[0], tol=1e-13)
+    b = pr.bodies[0]
+    u = O.S_block(1, b.X, b.Y) @ sol["sigma"]
+    rigid = O.K_matrix(b.X, b.centre) @ sol["out"][0]
+    assert rel_inf(u, rigid) < 1e-3  # MFS surface residual at N = 300 (a wrong formula gives O(1))
+
+
+# ---------------------------------------------------------------------------
+# several bodies
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_matvec_equals_assembled_square_system(kind):
+    wl = W.small_cluster(3, kind, 40, 85, seed=6)
+    pr = O.Problem.from_workload(wl)
+    A = pr.dense_matrix()
+    for seed in (7, 8):
+        g = W.random_vector(pr.n_gamma, seed)
+        assert rel_inf(pr.matvec(g), A @ g) < 1e-12
+    sol = pr.solve(wl.net[0], tol=1e-13)
+    assert rel_inf(sol["gamma"], np.linalg.solve(A, sol["b"])) < 1e-11
+    assert np.linalg.cond(A) < 100  # the one-body preconditioned system is well conditioned
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_rotated_shape_factor_equals_per_body_factor(kind):
+    wl = W.small_cluster(3, kind, 40, 85, seed=9)
+    a = O.Problem.from_workload(wl)
+    b = O.Problem.from_workload(wl, per_body=True)
+    g = W.random_vector(a.n_gamma, 10)
+    assert rel_inf(a.matvec(g), b.matvec(g)) < 1e-11
+
+
+def test_net_charge_force_torque_exact():
+    for kind in (W.STOKES, W.LAPLACE):
+        wl = W.small_cluster(3, kind, 40, 85, seed=11)
+        pr = O.Problem.from_workload(wl)
+        sol = pr.solve(wl.net[0], tol=1e-6)  # any gamma: the invariant holds regardless
+        for k, bd in enumerate(pr.bodies):
+            s = pr.sblock(sol["sigma"], k)
+            if kind == W.STOKES:
+                assert np.abs(O.K_matrix(bd.Y, bd.centre).T @ s - wl.net[0][k]).max() < 1e-12
+            else:
+                assert abs(s.sum() - wl.net[0][k]) < 1e-12
+
+
+def test_completion_is_minimum_norm():
+    wl = W.small_cluster(1, W.STOKES, 50, 100, seed=12)
+    b = O.Problem.from_workload(wl).bodies[0]
+    F = RNG.standard_normal(6)
+    lam0 = O.completion(W.STOKES, b.Y, b.centre, F)
+    KN = O.K_matrix(b.Y, b.centre)
+    ref = np.linalg.lstsq(KN.T, F, rcond=None)[0]  # minimum-norm solution of an underdetermined system
+    assert rel_inf(lam0, ref) < 1e-12
+
+
+def _mobility_matrix(pr, tol=1e-12):
+    P = len(pr.bodies)
+    Mm = np.zeros((6 * P, 6 * P))
+    for c in range(6 * P):
+        F = np.zeros((P, 6))
+        F.reshape(-1)[c] = 1.0
+        Mm[:, c] = pr.solve(F, tol=tol)["out"].reshape(-1)
+    return Mm
+
+
+def test_mobility_matrix_symmetric_positive_definite():
+    wl = W.small_cluster(3, W.STOKES, 80, 160, seed=13, axes=(1.0, 1.0, 1.0), gap=0.5)
+    Mm = _mobility_matrix(O.Problem.from_workload(wl))
+    asym = np.abs(Mm - Mm.T).max() / np.abs(Mm).max()
+    assert asym < 1e-3
+    assert np.linalg.eigvalsh(0.5 * (Mm + Mm.T)).min() > 0
+
+
+def test_translation_invariance_and_rotation_covariance():
+    wl = W.small_cluster(3, W.STOKES, 40, 85, seed=14)
+    F = wl.net[0]
+    U0 = O.Problem.from_workload(wl).solve(F, tol=1e-13)["out"]
+    shift = np.array([3.0, -7.0, 11.0])
+    wl2 = W.small_cluster(3, W.STOKES, 40, 85, seed=14)
+    wl2.centre = wl2.centre + shift
+    U1 = O.Problem.from_workload(wl2).solve(F, tol=1e-13)["out"]
+    assert rel_inf(U1, U0) < 1e-10
+    Q = W.random_rotation(np.random.default_rng(99))
+    wl3 = W.small_cluster(3, W.STOKES, 40, 85, seed=14)
+    wl3.centre = wl3.centre @ Q.T
+    wl3.rot = np.einsum("ab,kbc->kac", Q, wl3.rot)
+    F3 = np.concatenate([F[:, :3] @ Q.T, F[:, 3:] @ Q.T], axis=1)
+    U3 = O.Problem.from_workload(wl3).solve(F3, tol=1e-13)["out"]
+    U0r = np.concatenate([U0[:, :3] @ Q.T, U0[:, 3:] @ Q.T], axis=1)
+    assert rel_inf(U3, U0r) < 1e-10
+
+
+def _two_spheres(D, kind, n=200):
+    sh = W.Shape(np.ones(3), W.fibonacci_sphere(n, 0.7), W.fibonacci_sphere(2 * n, 1.0))
+    cen = np.array([[0.0, 0.0, 0.0], [D, 0.0, 0.0]])
+    rot = np.stack([np.eye(3), np.eye(3)])
+    return O.Problem(kind, [sh], cen, rot, np.zeros(2, np.int32))
+
+
+def test_two_body_far_field():
+    """phi_1 -> q1/(4 pi a) + q2/(4 pi D); v_1 -> f1/(6 pi a) + G(D) f2, errors O(D^-3)."""
+    q = np.array([1.0, -0.5])
+    f = np.array([[0.3, -0.2, 0.5, 0, 0, 0], [0.1, 0.4, -0.6, 0, 0, 0]])
+    errs_l, errs_s = [], []
+    for D in (10.0, 20.0):
+        phi = _two_spheres(D, W.LAPLACE).solve(q, tol=1e-13)["out"]
+        errs_l.append(abs(phi[0] - (q[0] / (4 * np.pi) + q[1] / (4 * np.pi * D))))
+        U = _two_spheres(D, W.STOKES).solve(f, tol=1e-13)["out"]
+        pred = f[0, :3] / (6 * np.pi) + O.stokeslet(np.array([-D, 0.0, 0.0])) @ f[1, :3]
+        errs_s.append(np.abs(U[0, :3] - pred).max())
+    assert errs_l[0] < 5.0 / 10.0 ** 3 and errs_l[1] < errs_l[0] / 4
+    assert errs_s[0] < 5.0 / 10.0 ** 3 and errs_s[1] < errs_s[0] / 4
+
+
+# ---------------------------------------------------------------------------
+# adjoint and gradients
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_adjoint_dot_product(kind):
+    wl = W.small_cluster(3, kind, 30, 70, seed=15)
+    pr = O.Problem.from_workload(wl)
+    x = W.random_vector(pr.n_gamma, 16)
+    y = W.random_vector(pr.n_gamma, 17)
+    assert abs(y @ pr.matvec(x) - x @ pr.matvec_T(y)) < 1e-12 * abs(y @ pr.matvec(x))
+
+
+def test_pair_gradient_matches_finite_differences():
+    wl = W.small_cluster(2, W.STOKES, 15, 30, seed=18)
+    pr = O.Problem.from_workload(wl)
+    w = RNG.standard_normal((pr.X.shape[0], 3))
+    s = RNG.standard_normal((pr.Y.shape[0], 3))
+    phi = lambda X, Y: np.sum(w * O.p2p(1, X, pr.trg_body, Y, pr.src_body, s, 1.0, True))
+    gx, gy = O.p2p_grad(1, pr.X, pr.trg_body, w, pr.Y, pr.src_body, s, 1.0, True)
+    h = 1e-6
+    for (i, a) in [(0, 0), (7, 2), (40, 1)]:
+        Xp, Xm = pr.X.copy(), pr.X.copy()
+        Xp[i, a] += h
+        Xm[i, a] -= h
+        assert abs((phi(Xp, pr.Y) - phi(Xm, pr.Y)) / (2 * h) - gx[i, a]) < 1e-7 * max(1, abs(gx[i, a]))
+    for (j, a) in [(0, 1), (20, 0)]:
+        Yp, Ym = pr.Y.copy(), pr.Y.copy()
+        Yp[j, a] += h
+        Ym[j, a] -= h
+        assert abs((phi(pr.X, Yp) - phi(pr.X, Ym)) / (2 * h) - gy[j, a]) < 1e-7 * max(1, abs(gy[j, a]))
+
+
+def test_velocity_loss_gradient_matches_finite_differences():
+    wl = W.small_cluster(3, W.STOKES, 30, 60, seed=19, axes=(1.0, 1.0, 1.0))
+    F = wl.net[0]
+
+    pr = O.Problem.from_workload(wl)
+    J, grad, _ = pr.velocity_loss_gradient(F, tol=1e-13)
+    h = 1e-5
+    for (k, a) in [(0, 0), (1, 2), (2, 1)]:
+        cp, cm = wl.centre.copy(), wl.centre.copy()
+        cp[k, a] += h
+        cm[k, a] -= h
+        Jp = np.sum(O.Problem(W.STOKES, wl.shapes, cp, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
+        Jm = np.sum(O.Problem(W.STOKES, wl.shapes, cm, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - grad[k, a]) < 1e-6 * np.abs(grad).max(), (k, a, fd, grad[k, a])
+
+
+# ---------------------------------------------------------------------------
+# a mistake planted in the oracle must be caught
+# ---------------------------------------------------------------------------
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    wl = W.single_sphere(W.STOKES)
+    F = wl.net[0][0]
+
+    def sphere_error():
+        U = O.Problem.from_workload(wl).solve(wl.net[0], tol=1e-12)["out"][0]
+        return max(rel_inf(U[:3], F[:3] / (6 * np.pi)), rel_inf(U[3:], F[3:] / (8 * np.pi)))
+
+    assert sphere_error() < 1e-6
+    # a sign error in the torque of the completion strengths (eq. (lambda02))
+    good_c = O.completion
+    monkeypatch.setattr(O, "completion", lambda kind, Y, c, net: good_c(kind, Y, c, np.asarray(net) *
+                                                                         np.array([1, 1, 1, -1, -1, -1])))
+    assert sphere_error() > 1e-2
+    monkeypatch.setattr(O, "completion", good_c)
+    # a dropped d d^T / r^2 term in the Stokeslet: the Stokes-equation pin fails
+    good_s = O.stokeslet
+
+    def no_dyad(d, mu=1.0):
+        r = np.linalg.norm(d, axis=-1)
+        return good_s(d, mu) - (d[..., :, None] * d[..., None, :]) / (8 * np.pi * mu * r ** 3)[..., None, None]
+
+    monkeypatch.setattr(O, "stokeslet", no_dyad)
+    with pytest.raises(AssertionError):
+        test_stokeslet_divergence_free_and_stokes_equation()
+    # the same mistake in the all-pairs sums: the drag closed form fails
+    good_p2p = O.p2p
+
+    def p2p_no_dyad(kind, X, tb, Y, sb, st, mu=1.0, skip_same_body=True):
+        S = O.S_block(kind, np.asarray(X), np.asarray(Y), mu)
+        mask = np.kron((np.asarray(tb)[:, None] != np.asarray(sb)[None, :]) | (not skip_same_body), np.ones((3, 3)))
+        return ((S * mask) @ np.asarray(st).reshape(-1)).reshape(-1, 3)
+
+    monkeypatch.setattr(O, "p2p", p2p_no_dyad)
+    assert sphere_error() > 1e-2
+    monkeypatch.setattr(O, "p2p", good_p2p)
+    monkeypatch.setattr(O, "stokeslet", good_s)
+    # a wrong normalisation of the Laplace kernel in the pair sums: the capacitance pin fails
+    wl_l = W.single_sphere(W.LAPLACE)
+
+    def p2p_double(kind, X, tb, Y, sb, st, mu=1.0, skip_same_body=True):
+        return 2.0 * good_p2p(kind, X, tb, Y, sb, st, mu, skip_same_body)
+
+    monkeypatch.setattr(O, "p2p", p2p_double)
+    phi = O.Problem.from_workload(wl_l).solve(np.ones(1), tol=1e-12)["out"][0]
+    assert abs(phi * 4 * np.pi - 1.0) > 1e-2
