@@ -1,0 +1,232 @@
+/*
+ * mfs.h -- C ABI of libmfs, the MI355X (gfx950) library for the
+ * one-body-preconditioned method of fundamental solutions (MFS) for 3D Laplace
+ * elastance and Stokes mobility problems (Broms, Barnett and Tornberg,
+ * arXiv 2409.04215).
+ *
+ * The library computes, on one GPU, the operator that GMRES applies in the
+ * paper's preconditioned square system (Section 3.3, eq. (2esysprec)):
+ *
+ *   (A gamma)^(k) = gamma^(k) + sum_{k' != k} S^(kk') (I - L^(k')) S_L^(k')+ gamma^(k'),
+ *
+ * its pieces (all-pairs fundamental-solution sums, per-body pseudo-inverse
+ * blocks, rigid-body / constant projection), the right-hand side, GMRES
+ * around it, the recovery of potentials or rigid velocities, and the adjoint
+ * of all of these for gradients with respect to particle centres.
+ *
+ * Conventions that hold for every entry point
+ * ------------------------------------------
+ * - Pointers marked [device] are GPU memory (e.g. torch.Tensor.data_ptr());
+ *   pointers marked [host] are CPU memory.  The caller owns every array it
+ *   passes; the library never frees caller memory and keeps no pointer to it
+ *   after the call returns.
+ * - Arrays are dense and row-major.  Points are [n][3] double; Stokes
+ *   strengths and velocities are [n][3] double (the paper's point-major
+ *   stacking, index 3(i-1)+a); Laplace strengths and potentials are [n] double.
+ * - Points are grouped by body and bodies by system (an independent
+ *   suspension).  Pairs in different systems never interact.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls are asynchronous on it unless stated otherwise.
+ * - Return value: MFS_OK (0) on success, a positive warning (outputs valid) or
+ *   a negative error.  Argument errors (MFS_EINVAL) are detected on the host
+ *   before any launch and leave every output untouched.  mfs_last_error()
+ *   returns a thread-local description of the last non-OK status.
+ * - Contents of device index arrays are not validated on the device.
+ * - A pair whose target and source coincide (r = 0) gives a non-finite term;
+ *   the method never forms one (proxies lie strictly inside their body and
+ *   bodies do not overlap).
+ */
+#ifndef MFS_H
+#define MFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MFS_OK = 0,
+    MFS_NOT_CONVERGED = 1, /* GMRES hit max_iter; outputs hold the best iterate */
+    MFS_EINVAL = -1,       /* bad argument; nothing was launched or written */
+    MFS_EHIP = -2,         /* a HIP runtime or library call failed */
+    MFS_ENOMEM = -3,       /* device allocation failed */
+    MFS_ENUMERIC = -4,     /* non-finite value, breakdown or singular factor */
+    MFS_EUNSUPPORTED = -5
+} mfs_status;
+
+typedef enum { MFS_LAPLACE = 0, MFS_STOKES = 1 } mfs_kind;
+
+/* MIXED: FP32 pair arithmetic (relative coordinates, FP64 accumulation per
+ * source tile) and FP32 MFMA pseudo-inverse blocks; FP64 projections and
+ * GMRES.  FP64: every step in FP64. */
+typedef enum { MFS_FP64 = 0, MFS_MIXED = 1 } mfs_precision;
+
+enum {
+    MFS_SKIP_SAME_BODY = 1, /* leave out pairs whose target and source share a body */
+    MFS_ACCUMULATE = 2,     /* out += sum instead of out = sum */
+    MFS_PROJECT = 4,        /* precond apply: also apply (I - L) */
+    MFS_TRANSPOSE = 8       /* precond apply: apply the transpose */
+};
+
+/* Thread-local text for the last non-OK status of this thread. */
+const char *mfs_last_error(void);
+/* Library version string. */
+const char *mfs_version(void);
+
+/* -------------------------------------------------------------------------
+ * All-pairs sums (the MFS representation, Section 2.1 eq. (rep) with the
+ * Laplace G = 1/(4 pi r), and Section 2.2 eq. (repS) with the Stokeslet
+ * eq. (stokeslet), G = (I + d d^T / r^2) / (8 pi mu r), d = x - y):
+ *
+ *   out_i (+)= sum_{j in sys(i), !(SKIP && body(j) == body(i))} G(x_i - y_j) s_j
+ *
+ * Structure arrays [host]:
+ *   sys_body_ptr [n_sys+1]  bodies of system s are [sys_body_ptr[s], sys_body_ptr[s+1])
+ *   body_trg_ptr [n_body+1] targets of body b are rows [body_trg_ptr[b], body_trg_ptr[b+1])
+ *   body_src_ptr [n_body+1] sources of body b are rows [body_src_ptr[b], body_src_ptr[b+1])
+ *   (n_body = sys_body_ptr[n_sys]; all three must be non-decreasing, start at 0,
+ *    and the totals must fit in int32.)
+ * Data arrays [device]: trg_xyz [n_trg][3], src_xyz [n_src][3],
+ *   src_q [n_src] / src_f [n_src][3], out_u [n_trg] / [n_trg][3].
+ * prec: MFS_MIXED or MFS_FP64.  mu must be finite and positive.
+ * Uses a library-owned device workspace (allocated on first use, grown as
+ * needed).  Errors: MFS_EINVAL for NULL data pointers, n_sys < 1, bad
+ * structure arrays, unknown flags or precision.
+ * ------------------------------------------------------------------------- */
+int mfs_p2p_laplace(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                    const double *src_q, double *out_u, int flags, int prec, void *stream);
+int mfs_p2p_stokes(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                   const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                   const double *src_f, double *out_u, double mu, int flags, int prec, void *stream);
+
+/* Backward of the pairing  Phi = sum_i w_i . out_i  for the sums above
+ * (flags as there; ACCUMULATE adds into every gradient that is requested):
+ *   grad_src  [n_src] / [n_src][3]  dPhi/ds_j   = sum_i G(y_j - x_i) w_i
+ *   grad_trg_xyz [n_trg][3]         dPhi/dx_i
+ *   grad_src_xyz [n_src][3]         dPhi/dy_j
+ * Any of the three gradient pointers may be NULL (that pass is skipped).
+ * trg_w is [n_trg] (Laplace) or [n_trg][3] (Stokes) [device].
+ * Pair gradient (d = x - y, r = |d|), Stokes:
+ *   dPhi_ij/dd = [-(w.s) d + (w.d) s + (s.d) w - 3 (w.d)(s.d) d / r^2] / (8 pi mu r^3);
+ * Laplace: dPhi_ij/dd = -w s d / (4 pi r^3).  Derived from the kernels above;
+ * the paper has no gradients. */
+int mfs_p2p_laplace_backward(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                             const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                             const double *src_q, const double *trg_w, double *grad_src_q,
+                             double *grad_trg_xyz, double *grad_src_xyz, int flags, int prec,
+                             void *stream);
+int mfs_p2p_stokes_backward(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                            const double *src_f, const double *trg_w, double *grad_src_f,
+                            double *grad_trg_xyz, double *grad_src_xyz, double mu, int flags, int prec,
+                            void *stream);
+
+/* -------------------------------------------------------------------------
+ * Plans.  A plan owns everything the solve reuses: device geometry, the
+ * per-shape pseudo-inverse factors of S_L = S^(kk)(I - L) + L_r (Section 3.3),
+ * per-body Gram inverses (K_N^T K_N)^{-1} (eq. (lambda02)), work tables and
+ * the Krylov workspace.
+ *
+ * Geometry: body b of shape s has world proxies y = centre_b + rot_b ytilde
+ * and collocation points x = centre_b + rot_b xtilde, with ytilde and xtilde
+ * the shape's local points.  Bodies sharing a shape and a kind share one FP64
+ * SVD of S_L in the shape frame; rotated copies apply it as Remark
+ * "congruent" states (lambda = R V Sigma^+ U^T R^T gamma).  No truncation:
+ * creation fails with MFS_ENUMERIC if sigma_min/sigma_max <= 1e-14.
+ *
+ * Vector layouts (all [device], FP64, bodies in order):
+ *   gamma / b / A gamma : body b holds dim_b * M_b entries (dim 1 Laplace, 3 Stokes)
+ *   lambda / strengths  : body b holds dim_b * N_b entries
+ *   net / out           : body b holds 1 (q or phi) or 6 ([f;t] or [v;omega]) entries
+ * mfs_plan_sizes reports the three totals.
+ * ------------------------------------------------------------------------- */
+typedef struct mfs_plan_s *mfs_plan;
+
+typedef struct {
+    int32_t precision;             /* MFS_MIXED or MFS_FP64: matvec used inside GMRES */
+    double mu;                     /* Stokes viscosity (> 0) */
+    int64_t n_sys;                 /* number of independent systems (>= 1) */
+    const int64_t *sys_body_ptr;   /* [host] [n_sys+1] */
+    const int32_t *sys_kind;       /* [host] [n_sys] MFS_LAPLACE or MFS_STOKES */
+    const double *centre;          /* [host] [n_body][3] */
+    const double *rot;             /* [host] [n_body][3][3] row-major rotation (x = c + R xtilde) */
+    const int32_t *shape_of_body;  /* [host] [n_body] */
+    int64_t n_shape;
+    const int32_t *shape_n_src;    /* [host] [n_shape] N per shape */
+    const int32_t *shape_n_trg;    /* [host] [n_shape] M per shape (M >= N) */
+    const double *shape_src;       /* [host] concatenated local proxies, sum(N) x 3 */
+    const double *shape_trg;       /* [host] concatenated local collocation points, sum(M) x 3 */
+} mfs_plan_desc;
+
+/* Builds a plan: uploads geometry, assembles S_L for every (shape, kind) in
+ * FP64 on the device, factors it (FP64 SVD), stores U^T and W = V Sigma^{-1}
+ * in FP64 and FP32, and the per-body Gram inverses.  Synchronous. */
+int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *desc, void *stream);
+int mfs_plan_destroy(mfs_plan plan);
+/* Totals of the three vector layouts above, and the smallest
+ * sigma_min/sigma_max over the plan's factors ([host] outputs, any may be NULL). */
+int mfs_plan_sizes(mfs_plan plan, int64_t *n_gamma, int64_t *n_lambda, int64_t *n_net,
+                   double *min_sigma_ratio);
+
+/* Completion strengths and right-hand side (eqs. (al0), (erhsK); (lambda01),
+ * (lambda02), (stou0)): s_0 = (q/N) 1 or K_N (K_N^T K_N)^{-1} [f; t] per body,
+ * then b = -u_0 with u_0 the pair sum over all pairs of the system, self
+ * included.  net [device] in the net layout; b [device] gamma layout;
+ * strength0 [device] lambda layout (may be NULL).  prec selects the pair
+ * arithmetic of u_0. */
+int mfs_rhs(mfs_plan plan, const double *net, double *b, double *strength0, int prec, void *stream);
+
+/* Per-body pseudo-inverse blocks (eq. (pseudo); Remark "congruent"):
+ *   out = S_L^+ in            (in: gamma layout, out: lambda layout)
+ *   flags & MFS_PROJECT:   out = (I - L) S_L^+ in
+ *   flags & MFS_TRANSPOSE: out = (S_L^+)^T in   (in: lambda layout, out: gamma
+ *                          layout; with PROJECT: (S_L^+)^T (I - L) in)
+ * prec selects FP32 MFMA (MFS_MIXED) or FP64 MFMA (MFS_FP64) GEMMs. */
+int mfs_precond_apply(mfs_plan plan, const double *in, double *out, int flags, int prec, void *stream);
+
+/* out = A gamma, the square operator of eq. (2esysprec) (gamma and out in the
+ * gamma layout, must not alias). */
+int mfs_matvec(mfs_plan plan, const double *gamma, double *out, int prec, void *stream);
+/* out = A^T w (derived: the paper has no adjoint). */
+int mfs_matvec_adjoint(mfs_plan plan, const double *w, double *out, int prec, void *stream);
+
+/* GMRES for A gamma = b (unrestarted per attempt, x0 = 0, classical
+ * Gram-Schmidt with reorthogonalisation, Givens rotations on the host, FP64).
+ * Every system stops on its own when ||r||_2 <= tol ||b||_2.  With a MIXED
+ * plan the Krylov matvec is the mixed one; each attempt ends with an FP64
+ * true-residual matvec, and systems above tol restart from their iterate on
+ * that residual (iterative refinement, at most max_refine restarts).
+ * iters [host][n_sys] receives the matvecs spent per system (mixed and FP64),
+ * relres [host][n_sys] the final relative residual (the true FP64 one for
+ * MIXED plans, the GMRES estimate for FP64 plans); either may be NULL.
+ * adjoint != 0 solves A^T gamma = b instead.  Synchronous.
+ * Returns MFS_NOT_CONVERGED if some system ends above tol. */
+int mfs_gmres_solve(mfs_plan plan, const double *b, double *gamma, double tol, int32_t max_iter,
+                    int32_t max_refine, int32_t adjoint, int32_t *iters, double *relres, void *stream);
+
+/* Recovery (Section 3.3; eqs. (vkal), (getU)): lambda = S_L^+ gamma (FP64
+ * factors), then out = phi = -mean(alpha) or [v; omega] = -K_N^T lambda per
+ * body (net layout).  sigma [device, lambda layout, may be NULL] receives the
+ * full strength (I - L) lambda + s_0 (strength0 may be NULL: taken as 0). */
+int mfs_extract(mfs_plan plan, const double *gamma, const double *strength0, double *out, double *sigma,
+                void *stream);
+
+/* Gradient of a loss J(out) with respect to the body centres, through the
+ * whole solve (bodies move rigidly with their centres; shapes, rotations and
+ * net quantities are held fixed).  Inputs: the forward solution gamma and
+ * strength0 (from mfs_rhs), grad_out = dJ/d(out) [device, net layout].
+ * Output: grad_centre [device][n_body][3].  One adjoint GMRES (A^T w = g with
+ * g = (S_L^+)^T dJ/dlambda), then the backward pair sums over off-body
+ * pairs.  iters/relres as for mfs_gmres_solve (adjoint solve).  Derived from
+ * the square system; the paper has no gradients.  Synchronous. */
+int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strength0, const double *grad_out,
+                       double *grad_centre, double tol, int32_t max_iter, int32_t max_refine,
+                       int32_t *iters, double *relres, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFS_H */

@@ -1,0 +1,652 @@
+// One-body (block-diagonal) operators, gfx950.
+//
+//  * Pseudo-inverse blocks S_L^+ v = V Sigma^+ (U^T v), applied in two steps
+//    and never formed (Section 2.3, eq. (pseudo)).  All bodies sharing a
+//    factor are one GEMM: the columns are the bodies' vectors rotated into the
+//    shape frame (Remark "congruent": lambda = R V Sigma^+ U^T R^T gamma).
+//    GEMMs run on the matrix cores: v_mfma_f32_32x32x2_f32 (mixed) or
+//    v_mfma_f64_16x16x4_f64 (FP64), LDS-staged 64x64 output tiles, one
+//    launch for every (factor, body-column) tile of every shape.
+//  * Projection (I - L): constants for Laplace (Section 3.1); rigid motions
+//    L = K_N (K_N^T K_N)^{-1} K_N^T for Stokes (Section 3.2).  Never formed:
+//    a 6-vector reduction w = K_N^T v, z = G^{-1} w, v - K_N z.  FP64.
+//  * Completion strengths (eqs. (al0), (lambda01), (lambda02)), recovery of
+//    phi / U (eqs. (vkal), (getU)), and setup assembly of
+//    S_L = S^(kk)(I - L) + L_r in FP64 (Section 3.3).
+#include "mfs_internal.h"
+
+namespace mfs {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM: C[:, col] = A_g * B[:, col] for every column of every group.
+// A_g row-major (M x K, lda = K) in a pool; B and C columns are contiguous
+// vectors at per-column element offsets.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmTile *__restrict__ tiles,
+                                                   const GemmGroup *__restrict__ groups,
+                                                   const T *__restrict__ Apool, const T *__restrict__ B,
+                                                   const int64_t *__restrict__ b_col_off, T *__restrict__ C,
+                                                   const int64_t *__restrict__ c_col_off) {
+    __shared__ T As[BM][BK + 1];
+    __shared__ T Bs[BN][BK + 1];
+    const GemmTile tl = tiles[blockIdx.x];
+    const GemmGroup g = groups[tl.group];
+    const T *A = Apool + g.a_off;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    // loader mapping: thread -> (row/col r, 4 consecutive k)
+    const int lr = tid >> 2, lk = (tid & 3) * 4;
+    const int arow = tl.m0 + lr;
+    const int bcol = tl.n0 + lr;
+    const bool a_ok = arow < g.M;
+    const bool b_ok = bcol < g.ncol;
+    const T *a_ptr = A + (int64_t)(a_ok ? arow : 0) * g.K;
+    const T *b_ptr = B + b_col_off[g.col_begin + (b_ok ? bcol : 0)];
+
+    if constexpr (sizeof(T) == 4) {
+        floatx16 acc = {};
+        for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + lk + q;
+                As[lr][lk + q] = (a_ok && k < g.K) ? a_ptr[k] : T(0);
+                Bs[lr][lk + q] = (b_ok && k < g.K) ? b_ptr[k] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 2) {
+                const float a = As[wm * 32 + (lane & 31)][kk + (lane >> 5)];
+                const float b = Bs[wn * 32 + (lane & 31)][kk + (lane >> 5)];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
+        const int col = tl.n0 + wn * 32 + (lane & 31);
+        if (col < g.ncol) {
+            T *c_ptr = C + c_col_off[g.col_begin + col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = tl.m0 + wm * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                if (row < g.M) c_ptr[row] = acc[r];
+            }
+        }
+    } else {
+        doublex4 acc[2][2] = {};
+        for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + lk + q;
+                As[lr][lk + q] = (a_ok && k < g.K) ? a_ptr[k] : T(0);
+                Bs[lr][lk + q] = (b_ok && k < g.K) ? b_ptr[k] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const double a = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const double b = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // D layout (16x16x4 f64, measured on gfx950): lane l, reg r -> row l/16 + 4 r, col l%16
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = tl.n0 + wn * 32 + j * 16 + (lane & 15);
+            if (col >= g.ncol) continue;
+            T *c_ptr = C + c_col_off[g.col_begin + col];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = tl.m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
+                    if (row < g.M) c_ptr[row] = acc[i][j][r];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction helper (256 threads)
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double (*sh)[NV]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[q] = x;
+    }
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sh[tid >> 6][q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = sh[0][q] + sh[1][q] + sh[2][q] + sh[3][q];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void rot_apply(const double *R, const double *v, bool transpose, double *o) {
+    if (!transpose) {
+        for (int r = 0; r < 3; ++r) o[r] = R[3 * r] * v[0] + R[3 * r + 1] * v[1] + R[3 * r + 2] * v[2];
+    } else {
+        for (int r = 0; r < 3; ++r) o[r] = R[r] * v[0] + R[3 + r] * v[1] + R[6 + r] * v[2];
+    }
+}
+
+// in (world frame fp64) -> out (shape frame, T); layout gamma (M points) or lambda (N points)
+template <class T>
+__global__ void rotate_in_kernel(BodyView bv, const double *__restrict__ in, T *__restrict__ out, int lam_layout) {
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = lam_layout ? bv.n_src[b] : bv.n_trg[b];
+    const int64_t off = lam_layout ? bv.lam_off[b] : bv.gam_off[b];
+    if (kind == MFS_LAPLACE) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) out[off + i] = (T)in[off + i];
+        return;
+    }
+    double R[9];
+    for (int q = 0; q < 9; ++q) R[q] = bv.rot[9 * b + q];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v[3] = {in[off + 3 * i], in[off + 3 * i + 1], in[off + 3 * i + 2]}, o[3];
+        rot_apply(R, v, true, o);
+        out[off + 3 * i] = (T)o[0];
+        out[off + 3 * i + 1] = (T)o[1];
+        out[off + 3 * i + 2] = (T)o[2];
+    }
+}
+
+// shape frame T -> world fp64 (rotate with R), layout gamma or lambda
+template <class T>
+__global__ void rotate_out_kernel(BodyView bv, const T *__restrict__ in, double *__restrict__ out, int lam_layout) {
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = lam_layout ? bv.n_src[b] : bv.n_trg[b];
+    const int64_t off = lam_layout ? bv.lam_off[b] : bv.gam_off[b];
+    if (kind == MFS_LAPLACE) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) out[off + i] = (double)in[off + i];
+        return;
+    }
+    double R[9];
+    for (int q = 0; q < 9; ++q) R[q] = bv.rot[9 * b + q];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v[3] = {(double)in[off + 3 * i], (double)in[off + 3 * i + 1], (double)in[off + 3 * i + 2]}, o[3];
+        rot_apply(R, v, false, o);
+        out[off + 3 * i] = o[0];
+        out[off + 3 * i + 1] = o[1];
+        out[off + 3 * i + 2] = o[2];
+    }
+}
+
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Strength of one pair-sum source record; the record array is chosen by the body kind.
+__device__ __forceinline__ void write_src(void *srcS, void *srcL, int prec, int kind, int64_t row, const double *v) {
+    if (kind == MFS_STOKES) {
+        if (!srcS) return;
+        if (prec == MFS_MIXED) {
+            SrcS32 *p = reinterpret_cast<SrcS32 *>(srcS) + row;
+            p->str = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+        } else {
+            SrcS64 *p = reinterpret_cast<SrcS64 *>(srcS) + row;
+            p->str[0] = v[0];
+            p->str[1] = v[1];
+            p->str[2] = v[2];
+        }
+    } else {
+        if (!srcL) return;
+        if (prec == MFS_MIXED) reinterpret_cast<float4 *>(srcL)[row].w = (float)v[0];
+        else reinterpret_cast<SrcL64 *>(srcL)[row].v[3] = v[0];
+    }
+}
+
+// Projection of one body's strength vector, world frame, FP64.
+// mode: 0 = (I - L) v ; also used to read the 6-vector / mean.
+// Stokes: w = K_N^T v = [sum v_j; sum d_j x v_j]; z = G^{-1} w; out_j = v_j - (z_v + z_w x d_j)
+template <class T>
+__global__ __launch_bounds__(256) void project_kernel(BodyView bv, const T *__restrict__ lam, int rotate, int project,
+                                                      double *__restrict__ out64, void *__restrict__ srcS,
+                                                      void *__restrict__ srcL, int src_prec) {
+    __shared__ double sh[4][6];
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    if (kind == MFS_LAPLACE) {
+        double s[1] = {0.0};
+        if (project) {
+            for (int j = threadIdx.x; j < n; j += blockDim.x) s[0] += (double)lam[off + j];
+            block_sum<1>(s, reinterpret_cast<double(*)[1]>(sh));
+        }
+        const double mean = project ? s[0] / n : 0.0;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const double v = (double)lam[off + j] - mean;
+            if (out64) out64[off + j] = v;
+            write_src(srcS, srcL, src_prec, kind, row0 + j, &v);
+        }
+        return;
+    }
+    double R[9];
+    for (int q = 0; q < 9; ++q) R[q] = bv.rot[9 * b + q];
+    double z[6] = {0, 0, 0, 0, 0, 0};
+    if (project) {
+        double w[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            double v[3] = {(double)lam[off + 3 * j], (double)lam[off + 3 * j + 1], (double)lam[off + 3 * j + 2]};
+            double vw[3];
+            if (rotate) rot_apply(R, v, false, vw);
+            else { vw[0] = v[0]; vw[1] = v[1]; vw[2] = v[2]; }
+            const double *d = bv.src_off64 + 4 * (row0 + j);
+            double c[3];
+            cross3(d, vw, c);
+            w[0] += vw[0]; w[1] += vw[1]; w[2] += vw[2];
+            w[3] += c[0]; w[4] += c[1]; w[5] += c[2];
+        }
+        block_sum<6>(w, sh);
+        const double *Gi = bv.gram_inv + 36 * b;
+        for (int r = 0; r < 6; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < 6; ++c) acc += Gi[6 * r + c] * w[c];
+            z[r] = acc;
+        }
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double v[3] = {(double)lam[off + 3 * j], (double)lam[off + 3 * j + 1], (double)lam[off + 3 * j + 2]};
+        double vw[3];
+        if (rotate) rot_apply(R, v, false, vw);
+        else { vw[0] = v[0]; vw[1] = v[1]; vw[2] = v[2]; }
+        if (project) {
+            const double *d = bv.src_off64 + 4 * (row0 + j);
+            double c[3];
+            cross3(z + 3, d, c);
+            vw[0] -= z[0] + c[0];
+            vw[1] -= z[1] + c[1];
+            vw[2] -= z[2] + c[2];
+        }
+        if (out64) {
+            out64[off + 3 * j] = vw[0];
+            out64[off + 3 * j + 1] = vw[1];
+            out64[off + 3 * j + 2] = vw[2];
+        }
+        write_src(srcS, srcL, src_prec, kind, row0 + j, vw);
+    }
+}
+
+// Completion strengths s_0 (eqs. (al0); (lambda01), (lambda02)).
+__global__ __launch_bounds__(256) void completion_kernel(BodyView bv, const double *__restrict__ net,
+                                                         double *__restrict__ s0, void *__restrict__ srcS,
+                                                         void *__restrict__ srcL, int src_prec) {
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    const double *nb = net + bv.net_off[b];
+    if (kind == MFS_LAPLACE) {
+        const double v = nb[0] / n;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            if (s0) s0[off + j] = v;
+            write_src(srcS, srcL, src_prec, kind, row0 + j, &v);
+        }
+        return;
+    }
+    const double *Gi = bv.gram_inv + 36 * b;
+    double z[6];
+    for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+        for (int c = 0; c < 6; ++c) acc += Gi[6 * r + c] * nb[c];
+        z[r] = acc;
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double *d = bv.src_off64 + 4 * (row0 + j);
+        double c[3];
+        cross3(z + 3, d, c);
+        double v[3] = {z[0] + c[0], z[1] + c[1], z[2] + c[2]};
+        if (s0) {
+            s0[off + 3 * j] = v[0];
+            s0[off + 3 * j + 1] = v[1];
+            s0[off + 3 * j + 2] = v[2];
+        }
+        write_src(srcS, srcL, src_prec, kind, row0 + j, v);
+    }
+}
+
+// Recovery: out = -mean(alpha) (Laplace) or -K_N^T lambda (Stokes); sigma = (I - L) lambda + s0.
+__global__ __launch_bounds__(256) void extract_kernel(BodyView bv, const double *__restrict__ lam,
+                                                      const double *__restrict__ s0, double *__restrict__ out,
+                                                      double *__restrict__ sigma) {
+    __shared__ double sh[4][6];
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    if (kind == MFS_LAPLACE) {
+        double s[1] = {0.0};
+        for (int j = threadIdx.x; j < n; j += blockDim.x) s[0] += lam[off + j];
+        block_sum<1>(s, reinterpret_cast<double(*)[1]>(sh));
+        const double mean = s[0] / n;
+        if (threadIdx.x == 0 && out) out[bv.net_off[b]] = -mean;
+        if (sigma)
+            for (int j = threadIdx.x; j < n; j += blockDim.x)
+                sigma[off + j] = lam[off + j] - mean + (s0 ? s0[off + j] : 0.0);
+        return;
+    }
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double *v = lam + off + 3 * j;
+        const double *d = bv.src_off64 + 4 * (row0 + j);
+        double c[3];
+        cross3(d, v, c);
+        w[0] += v[0]; w[1] += v[1]; w[2] += v[2];
+        w[3] += c[0]; w[4] += c[1]; w[5] += c[2];
+    }
+    block_sum<6>(w, sh);
+    if (threadIdx.x == 0 && out)
+        for (int q = 0; q < 6; ++q) out[bv.net_off[b] + q] = -w[q];
+    if (sigma) {
+        const double *Gi = bv.gram_inv + 36 * b;
+        double z[6];
+        for (int r = 0; r < 6; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < 6; ++c) acc += Gi[6 * r + c] * w[c];
+            z[r] = acc;
+        }
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const double *v = lam + off + 3 * j;
+            const double *d = bv.src_off64 + 4 * (row0 + j);
+            double c[3];
+            cross3(z + 3, d, c);
+            for (int q = 0; q < 3; ++q)
+                sigma[off + 3 * j + q] = v[q] - (z[q] + c[q]) + (s0 ? s0[off + 3 * j + q] : 0.0);
+        }
+    }
+}
+
+// dJ/dlambda from dJ/d(out): Stokes -K_N g (g = [gv; gw]); Laplace -(1/N) g.
+__global__ void grad_lambda_kernel(BodyView bv, const double *__restrict__ gout, double *__restrict__ glam) {
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    const double *g = gout + bv.net_off[b];
+    if (kind == MFS_LAPLACE) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) glam[off + j] = -g[0] / n;
+        return;
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double *d = bv.src_off64 + 4 * (row0 + j);
+        double c[3];
+        cross3(g + 3, d, c);
+        for (int q = 0; q < 3; ++q) glam[off + 3 * j + q] = -(g[q] + c[q]);
+    }
+}
+
+__global__ void set_src_strength_kernel(BodyView bv, const double *__restrict__ str, void *__restrict__ srcS,
+                                        void *__restrict__ srcL, int prec) {
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    const int dim = kind == MFS_STOKES ? 3 : 1;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) write_src(srcS, srcL, prec, kind, row0 + j, str + off + dim * j);
+}
+
+// grad_c[b] = sum over the body's targets of gt + sum over its sources of gs (fixed order)
+__global__ __launch_bounds__(256) void body_grad_reduce_kernel(const int32_t *__restrict__ trg_ptr,
+                                                               const int32_t *__restrict__ src_ptr,
+                                                               const double *__restrict__ gt,
+                                                               const double *__restrict__ gs,
+                                                               double *__restrict__ grad_c) {
+    __shared__ double sh[4][3];
+    const int64_t b = blockIdx.x;
+    double a[3] = {0, 0, 0};
+    for (int i = trg_ptr[b] + threadIdx.x; i < trg_ptr[b + 1]; i += blockDim.x)
+        for (int q = 0; q < 3; ++q) a[q] += gt[3 * (int64_t)i + q];
+    for (int j = src_ptr[b] + threadIdx.x; j < src_ptr[b + 1]; j += blockDim.x)
+        for (int q = 0; q < 3; ++q) a[q] += gs[3 * (int64_t)j + q];
+    block_sum<3>(a, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) grad_c[3 * b + q] = a[q];
+}
+
+// ---------------------------------------------------------------------------
+// Setup: S_L = S(I - L) + L_r in FP64, column-major (ld = dim*M), shape frame.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stokeslet64(const double *d, double mu, double G[3][3]) {
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double r = sqrt(r2);
+    const double pref = 1.0 / (8.0 * PI * mu * r);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) G[a][c] = pref * ((a == c ? 1.0 : 0.0) + d[a] * d[c] / r2);
+}
+
+// K rows at point p: [I, (p)_x], with (p)_x = [[0, p2, -p1], [-p2, 0, p0], [p1, -p0, 0]]
+__device__ __forceinline__ double Kentry(const double *p, int a, int q) {
+    if (q < 3) return a == q ? 1.0 : 0.0;
+    const int c = q - 3;
+    const double X[3][3] = {{0.0, p[2], -p[1]}, {-p[2], 0.0, p[0]}, {p[1], -p[0], 0.0}};
+    return X[a][c];
+}
+
+// Stokes step A: T_i = (S K_N)_i G^{-1} - K_M,i  (3 x 6 per target), work = [3M][6]
+__global__ void sl_stokes_T_kernel(int M, int N, const double *__restrict__ trg, const double *__restrict__ src,
+                                   const double *__restrict__ Gi, double mu, double *__restrict__ T) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double SK[3][6] = {};
+    const double *x = trg + 3 * i;
+    for (int j = 0; j < N; ++j) {
+        const double *y = src + 3 * j;
+        double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+        double G[3][3];
+        stokeslet64(d, mu, G);
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q < 6; ++q) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c) s += G[a][c] * Kentry(y, c, q);
+                SK[a][q] += s;
+            }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 6; ++q) {
+            double s = 0.0;
+            for (int p = 0; p < 6; ++p) s += SK[a][p] * Gi[6 * p + q];
+            T[(3 * i + a) * 6 + q] = s - Kentry(x, a, q);
+        }
+}
+
+// Stokes step B: SL[row, col] = S[row, col] - sum_q T[row][q] K_N[col][q]
+__global__ void sl_stokes_fill_kernel(int M, int N, const double *__restrict__ trg, const double *__restrict__ src,
+                                      const double *__restrict__ T, double mu, double *__restrict__ SL) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // target point
+    const int j = blockIdx.y;                              // source point
+    if (i >= M) return;
+    const double *x = trg + 3 * i;
+    const double *y = src + 3 * j;
+    double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+    double G[3][3];
+    stokeslet64(d, mu, G);
+    const int64_t ld = 3 * (int64_t)M;
+    for (int c = 0; c < 3; ++c) {
+        const int64_t col = 3 * j + c;
+        for (int a = 0; a < 3; ++a) {
+            double s = G[a][c];
+            for (int q = 0; q < 6; ++q) s -= T[(3 * i + a) * 6 + q] * Kentry(y, c, q);
+            SL[(3 * i + a) + col * ld] = s;
+        }
+    }
+}
+
+// Laplace: SL[i, j] = G_ij - mean_j' G_ij' + 1/N
+__global__ void sl_laplace_kernel(int M, int N, const double *__restrict__ trg, const double *__restrict__ src,
+                                  double *__restrict__ SL) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const double *x = trg + 3 * i;
+    double mean = 0.0;
+    for (int j = 0; j < N; ++j) {
+        const double *y = src + 3 * j;
+        const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+        mean += 1.0 / (4.0 * PI * sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    mean /= N;
+    for (int j = 0; j < N; ++j) {
+        const double *y = src + 3 * j;
+        const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+        SL[i + (int64_t)j * M] = 1.0 / (4.0 * PI * sqrt(d0 * d0 + d1 * d1 + d2 * d2)) - mean + 1.0 / N;
+    }
+}
+
+// dst[r][c] (row-major rows x cols) = src(r, c) * rs[r] * cs[c], src(r,c) = transposed ? src[c*ld + r] : src[r*ld + c]
+__global__ void make_factor_kernel(int rows, int cols, const double *__restrict__ src, int64_t ld, int transposed,
+                                   const double *__restrict__ rs, const double *__restrict__ cs,
+                                   double *__restrict__ d64, float *__restrict__ d32) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    double v = transposed ? src[(int64_t)c * ld + r] : src[(int64_t)r * ld + c];
+    if (rs) v *= rs[r];
+    if (cs) v *= cs[c];
+    d64[e] = v;
+    d32[e] = (float)v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int launch_gemm_f32(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const float *Apool, const float *B,
+                    const int64_t *b_col_off, float *C, const int64_t *c_col_off, hipStream_t s) {
+    if (n_tiles == 0) return MFS_OK;
+    gemm_kernel<float><<<n_tiles, 256, 0, s>>>(tiles, groups, Apool, B, b_col_off, C, c_col_off);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_gemm_f64(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const double *Apool,
+                    const double *B, const int64_t *b_col_off, double *C, const int64_t *c_col_off, hipStream_t s) {
+    if (n_tiles == 0) return MFS_OK;
+    gemm_kernel<double><<<n_tiles, 256, 0, s>>>(tiles, groups, Apool, B, b_col_off, C, c_col_off);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_rotate_in(const BodyView &bv, const double *in, void *out, bool out_f32, bool lam_layout, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    if (out_f32) rotate_in_kernel<float><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, in, (float *)out, lam_layout);
+    else rotate_in_kernel<double><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, in, (double *)out, lam_layout);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_rotate_out(const BodyView &bv, const void *in, bool in_f32, double *out, bool lam_layout, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    if (in_f32) rotate_out_kernel<float><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const float *)in, out, lam_layout);
+    else rotate_out_kernel<double><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const double *)in, out, lam_layout);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_project(const BodyView &bv, const void *lam, bool lam_f32, bool rotate, bool project, double *out64,
+                   void *srcS, void *srcL, int src_prec, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    if (lam_f32)
+        project_kernel<float><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const float *)lam, rotate, project, out64,
+                                                                  srcS, srcL, src_prec);
+    else
+        project_kernel<double><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const double *)lam, rotate, project, out64,
+                                                                   srcS, srcL, src_prec);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_completion(const BodyView &bv, const double *net, double *s0, void *srcS, void *srcL, int src_prec,
+                      hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    completion_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, net, s0, srcS, srcL, src_prec);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_extract(const BodyView &bv, const double *lam, const double *s0, double *out, double *sigma, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    extract_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, lam, s0, out, sigma);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    grad_lambda_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, grad_out, glam);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_set_src_strength(const BodyView &bv, const double *str, void *srcS, void *srcL, int prec, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    set_src_strength_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, str, srcS, srcL, prec);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_body_grad_reduce(int64_t n_body, const int32_t *trg_ptr, const int32_t *src_ptr, const double *gt,
+                            const double *gs, double *grad_c, hipStream_t s) {
+    if (n_body == 0) return MFS_OK;
+    body_grad_reduce_kernel<<<(unsigned)n_body, 256, 0, s>>>(trg_ptr, src_ptr, gt, gs, grad_c);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_assemble_SL(int kind, int M, int N, const double *trg, const double *src, const double *gram_inv6,
+                       double mu, double *SL, double *work, hipStream_t s) {
+    if (kind == MFS_LAPLACE) {
+        sl_laplace_kernel<<<(M + 127) / 128, 128, 0, s>>>(M, N, trg, src, SL);
+        MFS_HIP_TRY(hipGetLastError());
+        return MFS_OK;
+    }
+    sl_stokes_T_kernel<<<(M + 63) / 64, 64, 0, s>>>(M, N, trg, src, gram_inv6, mu, work);
+    MFS_HIP_TRY(hipGetLastError());
+    sl_stokes_fill_kernel<<<dim3((M + 127) / 128, N), 128, 0, s>>>(M, N, trg, src, work, mu, SL);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_make_factor(int rows, int cols, const double *src, int64_t ld, bool transposed, const double *rs,
+                       const double *cs, double *d64, float *d32, hipStream_t s) {
+    const int64_t n = (int64_t)rows * cols;
+    if (n == 0) return MFS_OK;
+    make_factor_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, cols, src, ld, transposed ? 1 : 0, rs, cs,
+                                                                  d64, d32);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+}  // namespace mfs

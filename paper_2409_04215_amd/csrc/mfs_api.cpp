@@ -1,0 +1,1289 @@
+// libmfs host side: argument checking, plans, the preconditioned operator
+// and GMRES drivers.  Every arithmetic step of the solve runs in the HIP
+// kernels of this library; this file only plans and sequences them.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "mfs_internal.h"
+
+namespace mfs {
+
+// kernels declared here to keep the internal header short
+int launch_make_factor(int rows, int cols, const double *src, int64_t ld, bool transposed, const double *rs,
+                       const double *cs, double *d64, float *d32, hipStream_t s);
+int launch_p2p_grad(const P2PPlan &pp, const P2PLaunch &L, const double *lane_vec, int64_t n_lane, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int DevBuf::reserve(size_t n) {
+    if (n <= bytes && ptr) return MFS_OK;
+    release();
+    if (n == 0) return MFS_OK;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? MFS_ENOMEM : MFS_EHIP,
+                    std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
+    }
+    bytes = n;
+    return MFS_OK;
+}
+
+int DevBuf::upload(const void *host, size_t n, hipStream_t s) {
+    MFS_TRY(reserve(n));
+    if (n) MFS_HIP_TRY(hipMemcpyAsync(ptr, host, n, hipMemcpyHostToDevice, s));
+    return MFS_OK;
+}
+
+template <class T>
+static int upload_vec(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+    return b.upload(v.data(), v.size() * sizeof(T), s);
+}
+
+// ---------------------------------------------------------------------------
+// pair-sum work items
+// ---------------------------------------------------------------------------
+int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, const int64_t *out_ptr, const int32_t *kind_of_body, double mu,
+                    int tpl, int min_items, hipStream_t s) {
+    pp.items.clear();
+    pp.tpl = tpl;
+    const int blk = 256 * tpl;
+    // bodies per source chunk: the largest chunk (fewest split slices) that still
+    // gives at least min_items items.
+    auto count_items = [&](int64_t chunk) {
+        int64_t n = 0;
+        for (int64_t sy = 0; sy < n_sys; ++sy) {
+            const int64_t b0 = sys_body_ptr[sy], b1 = sys_body_ptr[sy + 1];
+            const int64_t nt = body_trg_ptr[b1] - body_trg_ptr[b0];
+            if (nt == 0 || b1 == b0) continue;
+            n += ((nt + blk - 1) / blk) * ((b1 - b0 + chunk - 1) / chunk);
+        }
+        return n;
+    };
+    int64_t max_bodies = 1;
+    for (int64_t sy = 0; sy < n_sys; ++sy) max_bodies = std::max(max_bodies, sys_body_ptr[sy + 1] - sys_body_ptr[sy]);
+    int64_t chunk = max_bodies;
+    while (chunk > 1 && count_items(chunk) < min_items) chunk = (chunk + 1) / 2;
+    int n_split = 1;
+    for (int64_t sy = 0; sy < n_sys; ++sy)
+        n_split = std::max(n_split, (int)((sys_body_ptr[sy + 1] - sys_body_ptr[sy] + chunk - 1) / chunk));
+    struct Work { P2PItem it; double w; };
+    std::vector<Work> work;
+    for (int64_t sy = 0; sy < n_sys; ++sy) {
+        const int64_t b0 = sys_body_ptr[sy], b1 = sys_body_ptr[sy + 1];
+        if (b1 == b0) continue;
+        const int64_t T0 = body_trg_ptr[b0], T1 = body_trg_ptr[b1];
+        const int kind = kind_of_body[b0];
+        const double scale = kind == MFS_STOKES ? 1.0 / (8.0 * PI * mu) : 1.0 / (4.0 * PI);
+        const int dim = kind == MFS_STOKES ? 3 : 1;
+        for (int64_t t0 = T0; t0 < T1; t0 += blk) {
+            const int64_t t1 = std::min(t0 + blk, T1);
+            // every system writes all n_split slices (splits past its last body get an
+            // empty body range and write zeros), so the slice reduction reads no stale data
+            for (int sp = 0; sp < n_split; ++sp) {
+                const int64_t c0 = std::min(b1, b0 + (int64_t)sp * chunk), c1 = std::min(b1, c0 + chunk);
+                P2PItem it{};
+                it.out0 = out_ptr[b0] + dim * (t0 - T0);
+                it.scale = scale;
+                it.t0 = (int32_t)t0;
+                it.t1 = (int32_t)t1;
+                it.b0 = (int32_t)c0;
+                it.b1 = (int32_t)c1;
+                it.sys = (int32_t)sy;
+                it.split = sp;
+                it.kind = kind;
+                const double nsrc = (double)(body_src_ptr[c1] - body_src_ptr[c0]);
+                work.push_back({it, nsrc * (double)(t1 - t0) * (kind == MFS_STOKES ? 2.5 : 1.0)});
+            }
+        }
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.w > b.w; });
+    pp.items.reserve(work.size());
+    for (auto &w : work) pp.items.push_back(w.it);
+    pp.n_split = n_split;
+    if (!pp.items.empty()) MFS_TRY(upload_vec(pp.d_items, pp.items, s));
+    return MFS_OK;
+}
+
+}  // namespace mfs
+
+using namespace mfs;
+
+// ---------------------------------------------------------------------------
+// library-owned workspace for the standalone entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Workspace {
+    DevBuf centre, trg_body, src_body, trg_ptr, src_ptr, trg_off, src_ops, partial, tmp;
+};
+Workspace &workspace() {
+    static thread_local Workspace w;
+    return w;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_structure(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, int64_t *n_body, int64_t *n_trg, int64_t *n_src) {
+    if (n_sys < 1) return fail(MFS_EINVAL, "n_sys must be >= 1");
+    if (!sys_body_ptr || !body_trg_ptr || !body_src_ptr) return fail(MFS_EINVAL, "NULL structure array");
+    if (sys_body_ptr[0] != 0) return fail(MFS_EINVAL, "sys_body_ptr[0] must be 0");
+    for (int64_t s = 0; s < n_sys; ++s)
+        if (sys_body_ptr[s + 1] < sys_body_ptr[s]) return fail(MFS_EINVAL, "sys_body_ptr not non-decreasing");
+    const int64_t nb = sys_body_ptr[n_sys];
+    if (body_trg_ptr[0] != 0 || body_src_ptr[0] != 0) return fail(MFS_EINVAL, "body pointers must start at 0");
+    for (int64_t b = 0; b < nb; ++b)
+        if (body_trg_ptr[b + 1] < body_trg_ptr[b] || body_src_ptr[b + 1] < body_src_ptr[b])
+            return fail(MFS_EINVAL, "body pointers not non-decreasing");
+    if (body_trg_ptr[nb] > INT32_MAX || body_src_ptr[nb] > INT32_MAX)
+        return fail(MFS_EINVAL, "point counts must fit in int32");
+    *n_body = nb;
+    *n_trg = body_trg_ptr[nb];
+    *n_src = body_src_ptr[nb];
+    return MFS_OK;
+}
+
+int check_prec(int prec) {
+    if (prec != MFS_MIXED && prec != MFS_FP64) return fail(MFS_EINVAL, "unknown precision");
+    return MFS_OK;
+}
+
+// Sets up the split representation of standalone FP64 inputs in the workspace.
+int standalone_geometry(Workspace &ws, int64_t n_body, int64_t n_trg, int64_t n_src, const int64_t *body_trg_ptr,
+                        const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, int prec,
+                        hipStream_t s) {
+    std::vector<int32_t> tp(body_trg_ptr, body_trg_ptr + n_body + 1), sp(body_src_ptr, body_src_ptr + n_body + 1);
+    MFS_TRY(upload_vec(ws.trg_ptr, tp, s));
+    MFS_TRY(upload_vec(ws.src_ptr, sp, s));
+    MFS_TRY(ws.centre.reserve(std::max<int64_t>(1, n_body) * 3 * sizeof(double)));
+    MFS_TRY(ws.trg_body.reserve(std::max<int64_t>(1, n_trg) * sizeof(int32_t)));
+    MFS_TRY(ws.src_body.reserve(std::max<int64_t>(1, n_src) * sizeof(int32_t)));
+    MFS_TRY(launch_body_refpoint(n_body, ws.src_ptr.as<int32_t>(), ws.trg_ptr.as<int32_t>(), src_xyz, trg_xyz,
+                                 ws.centre.as<double>(), s));
+    MFS_TRY(launch_fill_body_ids(n_body, ws.trg_ptr.as<int32_t>(), ws.trg_body.as<int32_t>(), s));
+    MFS_TRY(launch_fill_body_ids(n_body, ws.src_ptr.as<int32_t>(), ws.src_body.as<int32_t>(), s));
+    MFS_TRY(ws.trg_off.reserve(std::max<int64_t>(1, n_trg) * (prec == MFS_MIXED ? 16 : 32)));
+    MFS_TRY(launch_make_trg_off(n_trg, trg_xyz, ws.trg_body.as<int32_t>(), ws.centre.as<double>(), prec,
+                                ws.trg_off.ptr, s));
+    return MFS_OK;
+}
+
+int p2p_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                   const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, const double *str,
+                   double *out, double mu, int flags, int prec, void *stream) {
+    int64_t nb, nt, ns;
+    MFS_TRY(check_structure(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, &nb, &nt, &ns));
+    MFS_TRY(check_prec(prec));
+    if (flags & ~(MFS_SKIP_SAME_BODY | MFS_ACCUMULATE)) return fail(MFS_EINVAL, "unknown flags");
+    if (kind == MFS_STOKES && !finite_pos(mu)) return fail(MFS_EINVAL, "mu must be finite and > 0");
+    if ((nt > 0 && (!trg_xyz || !out)) || (ns > 0 && (!src_xyz || !str)))
+        return fail(MFS_EINVAL, "NULL data pointer");
+    if (nt == 0) return MFS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = workspace();
+    MFS_TRY(standalone_geometry(ws, nb, nt, ns, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, prec, s));
+    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
+                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
+    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
+    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), str, prec,
+                            ws.src_ops.ptr, s));
+    const int dim = kind == MFS_STOKES ? 3 : 1;
+    std::vector<int64_t> out_ptr(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
+    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
+    P2PPlan pp;
+    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), mu, 1,
+                            2048, s));
+    P2PLaunch L;
+    L.prec = prec;
+    L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
+    L.accumulate = (flags & MFS_ACCUMULATE) != 0;
+    L.centre = ws.centre.as<double>();
+    L.trg_body = ws.trg_body.as<int32_t>();
+    L.src_ptr = ws.src_ptr.as<int32_t>();
+    L.trg_off = ws.trg_off.ptr;
+    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
+    L.out = out;
+    L.n_val = dim * nt;
+    if (pp.n_split > 1) {
+        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * L.n_val * sizeof(double)));
+        L.partial = ws.partial.as<double>();
+    }
+    MFS_TRY(launch_p2p(pp, L, s));
+    // pp.d_items must stay alive until the kernels have read it
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    return MFS_OK;
+}
+
+// Position gradient of the pairing over one orientation: lanes carry lane_vec
+// ([n_lane][dim]), sources carry src_str; out_grad [n_lane][3].
+int p2p_grad_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *lane_ptr,
+                        const int64_t *src_ptr, const double *lane_xyz, const double *src_xyz, const double *lane_vec,
+                        const double *src_str, double *out_grad, double mu, int flags, int prec, hipStream_t s) {
+    const int64_t nb = sys_body_ptr[n_sys], nl = lane_ptr[nb], ns = src_ptr[nb];
+    if (nl == 0) return MFS_OK;
+    Workspace &ws = workspace();
+    MFS_TRY(standalone_geometry(ws, nb, nl, ns, lane_ptr, src_ptr, lane_xyz, src_xyz, prec, s));
+    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
+                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
+    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
+    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), src_str, prec,
+                            ws.src_ops.ptr, s));
+    const int dim = kind == MFS_STOKES ? 3 : 1;
+    std::vector<int64_t> out_ptr(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * lane_ptr[b];
+    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
+    P2PPlan pp;
+    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, lane_ptr, src_ptr, out_ptr.data(), kob.data(), mu, 1, 2048, s));
+    P2PLaunch L;
+    L.prec = prec;
+    L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
+    L.accumulate = (flags & MFS_ACCUMULATE) != 0;
+    L.centre = ws.centre.as<double>();
+    L.trg_body = ws.trg_body.as<int32_t>();
+    L.src_ptr = ws.src_ptr.as<int32_t>();
+    L.trg_off = ws.trg_off.ptr;
+    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
+    L.out = out_grad;
+    L.n_val = 3 * nl;
+    if (pp.n_split > 1) {
+        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * 3 * nl * sizeof(double)));
+        L.partial = ws.partial.as<double>();
+    }
+    MFS_TRY(launch_p2p_grad(pp, L, lane_vec, nl, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    return MFS_OK;
+}
+
+int p2p_backward_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                            const double *src_s, const double *trg_w, double *grad_src, double *grad_trg_xyz,
+                            double *grad_src_xyz, double mu, int flags, int prec, void *stream) {
+    int64_t nb, nt, ns;
+    MFS_TRY(check_structure(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, &nb, &nt, &ns));
+    MFS_TRY(check_prec(prec));
+    if (flags & ~(MFS_SKIP_SAME_BODY | MFS_ACCUMULATE)) return fail(MFS_EINVAL, "unknown flags");
+    if (kind == MFS_STOKES && !finite_pos(mu)) return fail(MFS_EINVAL, "mu must be finite and > 0");
+    if ((nt > 0 && (!trg_xyz || !trg_w)) || (ns > 0 && (!src_xyz || !src_s)))
+        return fail(MFS_EINVAL, "NULL data pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (grad_src)  // dPhi/ds_j = sum_i G(y_j - x_i) w_i: the sum with the roles swapped
+        MFS_TRY(p2p_standalone(kind, n_sys, sys_body_ptr, body_src_ptr, body_trg_ptr, src_xyz, trg_xyz, trg_w, grad_src,
+                               mu, flags, prec, stream));
+    if (grad_trg_xyz)
+        MFS_TRY(p2p_grad_standalone(kind, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, trg_w,
+                                    src_s, grad_trg_xyz, mu, flags, prec, s));
+    if (grad_src_xyz)  // odd, symmetric pair term: the same kernel on the swapped orientation
+        MFS_TRY(p2p_grad_standalone(kind, n_sys, sys_body_ptr, body_src_ptr, body_trg_ptr, src_xyz, trg_xyz, src_s,
+                                    trg_w, grad_src_xyz, mu, flags, prec, s));
+    return MFS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Factor {
+    int kind, shape, dN, dM;
+    int64_t ut_off, w_off, u_off, wt_off;
+    double ratio;
+};
+
+struct mfs_plan_s {
+    int prec = MFS_MIXED;
+    double mu = 1.0;
+    int64_t n_sys = 0, n_body = 0;
+    std::vector<int64_t> sys_body_ptr;
+    std::vector<int32_t> sys_kind;
+    std::vector<int32_t> kind, n_src, n_trg, factor_of_body;
+    std::vector<int64_t> gam_off, lam_off, net_off;  // n_body + 1 entries
+    std::vector<int64_t> src_row, trg_row;           // n_body + 1 entries
+    int64_t n_gamma = 0, n_lambda = 0, n_net = 0, n_srcp = 0, n_trgp = 0;
+    double min_ratio = 1.0;
+
+    // device per-body arrays
+    DevBuf d_kind, d_nsrc, d_ntrg, d_gam_off, d_lam_off, d_net_off, d_src_row32, d_trg_row32, d_rot, d_gram_inv,
+        d_centre, d_src_row64, d_trg_row64;
+    DevBuf d_src_off64, d_trg_off64, d_src_off32, d_trg_off32;  // [n][4] double / float4
+    DevBuf d_src_body, d_trg_body;
+    // pair operands: forward (sources = proxies), transposed (sources = collocation points)
+    DevBuf fS32, fL32, fS64, fL64, tS32, tL32, tS64, tL64;
+    // factors
+    DevBuf A32, A64;
+    std::vector<Factor> factors;
+    DevBuf d_col_gam, d_col_lam;
+    DevBuf g_fwd1, g_fwd2, g_tr1, g_tr2, tiles_N, tiles_M;
+    int n_tiles_N = 0, n_tiles_M = 0;
+    // pair plans
+    P2PPlan p2p_fwd, p2p_tr, p2p_fwd1, p2p_tr1;  // *1: one target per lane (gradient kernels)
+    // workspace
+    DevBuf ws_g32, ws_l32a, ws_l32b, ws_g64, ws_l64a, ws_l64b, ws_l64c, partial, sys_active;
+    // GMRES
+    int gm_cap = 0;
+    DevBuf V, Wv, R, X, dots_partial, dots, nrm, coef, chunks, sys_chunk_ptr, flag;
+    // backward
+    DevBuf bw_sigma, bw_glam, bw_g, bw_w, bw_gt, bw_gs;
+    std::vector<VecChunk> h_chunks;
+    std::vector<int32_t> h_sys_chunk_ptr;
+
+    BodyView view() const {
+        BodyView v;
+        v.n_body = n_body;
+        v.kind = d_kind.as<int32_t>();
+        v.n_src = d_nsrc.as<int32_t>();
+        v.n_trg = d_ntrg.as<int32_t>();
+        v.gam_off = d_gam_off.as<int64_t>();
+        v.lam_off = d_lam_off.as<int64_t>();
+        v.net_off = d_net_off.as<int64_t>();
+        v.src_row = d_src_row32.as<int32_t>();
+        v.trg_row = d_trg_row32.as<int32_t>();
+        v.rot = d_rot.as<double>();
+        v.gram_inv = d_gram_inv.as<double>();
+        v.src_off64 = d_src_off64.as<double>();
+        return v;
+    }
+};
+
+namespace {
+
+// 6x6 inverse by Gauss-Jordan with partial pivoting (FP64, host).
+bool inv6(const double *A, double *Ai) {
+    double M[6][12];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 12; ++c) M[r][c] = c < 6 ? A[6 * r + c] : (c - 6 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 6; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 6; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
+        if (!(std::fabs(M[p][c]) > 0.0)) return false;
+        if (p != c)
+            for (int k = 0; k < 12; ++k) std::swap(M[p][k], M[c][k]);
+        const double d = M[c][c];
+        for (int k = 0; k < 12; ++k) M[c][k] /= d;
+        for (int r = 0; r < 6; ++r)
+            if (r != c) {
+                const double f = M[r][c];
+                if (f != 0.0)
+                    for (int k = 0; k < 12; ++k) M[r][k] -= f * M[c][k];
+            }
+    }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) Ai[6 * r + c] = M[r][c + 6];
+    return true;
+}
+
+// Gram matrix K^T K of rigid-body rows [I, (p)_x] over points p (relative to the centre).
+void gram6(const double *pts, int n, double *G) {
+    std::fill(G, G + 36, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double *p = pts + 3 * j;
+        const double X[3][3] = {{0.0, p[2], -p[1]}, {-p[2], 0.0, p[0]}, {p[1], -p[0], 0.0}};
+        double K[3][6];
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q < 6; ++q) K[a][q] = q < 3 ? (a == q ? 1.0 : 0.0) : X[a][q - 3];
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a) s += K[a][r] * K[a][c];
+                G[6 * r + c] += s;
+            }
+    }
+}
+
+// world-frame Gram inverse: R2 G0^{-1} R2^T with R2 = diag(R, R)
+void rotate_gram(const double *G0i, const double *R, double *Gi) {
+    double R2[6][6] = {};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R2[a][b] = R2[a + 3][b + 3] = R[3 * a + b];
+    double T[6][6];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += R2[r][k] * G0i[6 * k + c];
+            T[r][c] = s;
+        }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += T[r][k] * R2[c][k];
+            Gi[6 * r + c] = s;
+        }
+}
+
+int build_gemm_tables(mfs_plan p, hipStream_t s) {
+    // groups: per factor, the list of its bodies as columns
+    std::vector<std::vector<int32_t>> cols(p->factors.size());
+    for (int64_t b = 0; b < p->n_body; ++b) cols[p->factor_of_body[b]].push_back((int32_t)b);
+    std::vector<int64_t> col_gam, col_lam;
+    std::vector<GemmGroup> g1, g2, t1, t2;
+    std::vector<GemmTile> tiN, tiM;
+    for (size_t f = 0; f < p->factors.size(); ++f) {
+        const Factor &F = p->factors[f];
+        const int32_t cb = (int32_t)col_gam.size(), nc = (int32_t)cols[f].size();
+        for (int32_t b : cols[f]) {
+            col_gam.push_back(p->gam_off[b]);
+            col_lam.push_back(p->lam_off[b]);
+        }
+        g1.push_back(GemmGroup{F.dN, F.dM, cb, nc, F.ut_off});
+        g2.push_back(GemmGroup{F.dN, F.dN, cb, nc, F.w_off});
+        t1.push_back(GemmGroup{F.dN, F.dN, cb, nc, F.wt_off});
+        t2.push_back(GemmGroup{F.dM, F.dN, cb, nc, F.u_off});
+        for (int m0 = 0; m0 < F.dN; m0 += 64)
+            for (int n0 = 0; n0 < nc; n0 += 64) tiN.push_back(GemmTile{(int32_t)f, m0, n0, 0});
+        for (int m0 = 0; m0 < F.dM; m0 += 64)
+            for (int n0 = 0; n0 < nc; n0 += 64) tiM.push_back(GemmTile{(int32_t)f, m0, n0, 0});
+    }
+    MFS_TRY(upload_vec(p->d_col_gam, col_gam, s));
+    MFS_TRY(upload_vec(p->d_col_lam, col_lam, s));
+    MFS_TRY(upload_vec(p->g_fwd1, g1, s));
+    MFS_TRY(upload_vec(p->g_fwd2, g2, s));
+    MFS_TRY(upload_vec(p->g_tr1, t1, s));
+    MFS_TRY(upload_vec(p->g_tr2, t2, s));
+    MFS_TRY(upload_vec(p->tiles_N, tiN, s));
+    MFS_TRY(upload_vec(p->tiles_M, tiM, s));
+    p->n_tiles_N = (int)tiN.size();
+    p->n_tiles_M = (int)tiM.size();
+    return MFS_OK;
+}
+
+// FP64 SVD of every (shape, kind) S_L on the device; fills the factor pools.
+int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t> &shape_src_off,
+                  const std::vector<int64_t> &shape_trg_off, hipStream_t s) {
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(MFS_EHIP, "rocblas_create_handle failed");
+    std::unique_ptr<rocblas_handle, void (*)(rocblas_handle *)> guard(&h, [](rocblas_handle *hh) {
+        rocblas_destroy_handle(*hh);
+    });
+    rocblas_set_stream(h, s);
+    // pool layout
+    int64_t pool = 0;
+    for (auto &F : p->factors) {
+        F.ut_off = pool;
+        pool += (int64_t)F.dN * F.dM;
+        F.w_off = pool;
+        pool += (int64_t)F.dN * F.dN;
+        F.wt_off = pool;
+        pool += (int64_t)F.dN * F.dN;
+        F.u_off = pool;
+        pool += (int64_t)F.dM * F.dN;
+    }
+    MFS_TRY(p->A64.reserve(std::max<int64_t>(1, pool) * sizeof(double)));
+    MFS_TRY(p->A32.reserve(std::max<int64_t>(1, pool) * sizeof(float)));
+    DevBuf SL, Ub, Vb, Sv, E, info, work, pts, gi, ones;
+    for (auto &F : p->factors) {
+        const int N = d->shape_n_src[F.shape], M = d->shape_n_trg[F.shape];
+        const int m = F.dM, n = F.dN;
+        MFS_TRY(SL.reserve((size_t)m * n * sizeof(double)));
+        MFS_TRY(Ub.reserve((size_t)m * n * sizeof(double)));
+        MFS_TRY(Vb.reserve((size_t)n * n * sizeof(double)));
+        MFS_TRY(Sv.reserve((size_t)n * sizeof(double)));
+        MFS_TRY(E.reserve((size_t)n * sizeof(double)));
+        MFS_TRY(info.reserve(sizeof(rocblas_int)));
+        MFS_TRY(work.reserve((size_t)3 * M * 6 * sizeof(double)));
+        std::vector<double> hp(3 * (size_t)(M + N));
+        std::memcpy(hp.data(), d->shape_trg + 3 * shape_trg_off[F.shape], 3 * (size_t)M * sizeof(double));
+        std::memcpy(hp.data() + 3 * (size_t)M, d->shape_src + 3 * shape_src_off[F.shape], 3 * (size_t)N * sizeof(double));
+        MFS_TRY(upload_vec(pts, hp, s));
+        double G[36], Gi[36];
+        gram6(d->shape_src + 3 * shape_src_off[F.shape], N, G);
+        if (F.kind == MFS_STOKES && !inv6(G, Gi)) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
+        std::vector<double> gv(Gi, Gi + 36);
+        MFS_TRY(upload_vec(gi, gv, s));
+        MFS_TRY(launch_assemble_SL(F.kind, M, N, pts.as<double>(), pts.as<double>() + 3 * (size_t)M, gi.as<double>(),
+                                   p->mu, SL.as<double>(), work.as<double>(), s));
+        rocblas_status st = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, m, n,
+                                             SL.as<double>(), m, Sv.as<double>(), Ub.as<double>(), m, Vb.as<double>(),
+                                             n, E.as<double>(), rocblas_outofplace, info.as<rocblas_int>());
+        if (st != rocblas_status_success) return fail(MFS_EHIP, "rocsolver_dgesvd failed");
+        std::vector<double> sv(n);
+        rocblas_int hinfo = 0;
+        MFS_HIP_TRY(hipMemcpyAsync(sv.data(), Sv.ptr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipMemcpyAsync(&hinfo, info.ptr, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+        if (hinfo != 0) return fail(MFS_ENUMERIC, "SVD did not converge");
+        F.ratio = sv[n - 1] / sv[0];
+        p->min_ratio = std::min(p->min_ratio, F.ratio);
+        if (!(F.ratio > 1e-14))
+            return fail(MFS_ENUMERIC, "sigma_min/sigma_max = " + std::to_string(F.ratio) + " <= 1e-14");
+        std::vector<double> inv(n);
+        for (int i = 0; i < n; ++i) inv[i] = 1.0 / sv[i];
+        MFS_TRY(upload_vec(ones, inv, s));
+        double *A64 = p->A64.as<double>();
+        float *A32 = p->A32.as<float>();
+        // U^T (n x m): row r = column r of U (column-major, ld m)
+        MFS_TRY(launch_make_factor(n, m, Ub.as<double>(), m, false, nullptr, nullptr, A64 + F.ut_off, A32 + F.ut_off, s));
+        // U (m x n) row-major: U[r][c] = Ucm[c*m + r]
+        MFS_TRY(launch_make_factor(m, n, Ub.as<double>(), m, true, nullptr, nullptr, A64 + F.u_off, A32 + F.u_off, s));
+        // W = V Sigma^{-1}: the V^T output (column-major, ld n) read row-major is V
+        MFS_TRY(launch_make_factor(n, n, Vb.as<double>(), n, false, nullptr, ones.as<double>(), A64 + F.w_off,
+                                   A32 + F.w_off, s));
+        // W^T = Sigma^{-1} V^T
+        MFS_TRY(launch_make_factor(n, n, Vb.as<double>(), n, true, ones.as<double>(), nullptr, A64 + F.wt_off,
+                                   A32 + F.wt_off, s));
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return MFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mfs_last_error(void) { return g_last_error.c_str(); }
+const char *mfs_version(void) { return "libmfs 0.1 (gfx950)"; }
+
+int mfs_p2p_laplace(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, const double *src_q,
+                    double *out_u, int flags, int prec, void *stream) {
+    return p2p_standalone(MFS_LAPLACE, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_q, out_u,
+                          1.0, flags, prec, stream);
+}
+
+int mfs_p2p_stokes(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                   const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, const double *src_f,
+                   double *out_u, double mu, int flags, int prec, void *stream) {
+    return p2p_standalone(MFS_STOKES, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f, out_u,
+                          mu, flags, prec, stream);
+}
+
+int mfs_p2p_laplace_backward(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                             const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                             const double *src_q, const double *trg_w, double *grad_src_q, double *grad_trg_xyz,
+                             double *grad_src_xyz, int flags, int prec, void *stream) {
+    return p2p_backward_standalone(MFS_LAPLACE, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_q,
+                                   trg_w, grad_src_q, grad_trg_xyz, grad_src_xyz, 1.0, flags, prec, stream);
+}
+
+int mfs_p2p_stokes_backward(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                            const double *src_f, const double *trg_w, double *grad_src_f, double *grad_trg_xyz,
+                            double *grad_src_xyz, double mu, int flags, int prec, void *stream) {
+    return p2p_backward_standalone(MFS_STOKES, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f,
+                                   trg_w, grad_src_f, grad_trg_xyz, grad_src_xyz, mu, flags, prec, stream);
+}
+
+int mfs_plan_destroy(mfs_plan plan) {
+    if (!plan) return MFS_OK;
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return MFS_OK;
+}
+
+int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
+    if (!out || !d) return fail(MFS_EINVAL, "NULL plan or descriptor");
+    *out = nullptr;
+    if (d->precision != MFS_MIXED && d->precision != MFS_FP64) return fail(MFS_EINVAL, "unknown precision");
+    if (d->n_sys < 1 || !d->sys_body_ptr || !d->sys_kind) return fail(MFS_EINVAL, "bad system description");
+    if (d->sys_body_ptr[0] != 0) return fail(MFS_EINVAL, "sys_body_ptr[0] must be 0");
+    for (int64_t sy = 0; sy < d->n_sys; ++sy) {
+        if (d->sys_body_ptr[sy + 1] < d->sys_body_ptr[sy]) return fail(MFS_EINVAL, "sys_body_ptr not non-decreasing");
+        if (d->sys_kind[sy] != MFS_LAPLACE && d->sys_kind[sy] != MFS_STOKES) return fail(MFS_EINVAL, "unknown kind");
+    }
+    const int64_t nb = d->sys_body_ptr[d->n_sys];
+    if (nb < 1) return fail(MFS_EINVAL, "no bodies");
+    if (!d->centre || !d->rot || !d->shape_of_body) return fail(MFS_EINVAL, "NULL body arrays");
+    if (d->n_shape < 1 || !d->shape_n_src || !d->shape_n_trg || !d->shape_src || !d->shape_trg)
+        return fail(MFS_EINVAL, "bad shape description");
+    if (!finite_pos(d->mu)) return fail(MFS_EINVAL, "mu must be finite and > 0");
+    std::vector<int64_t> sso(d->n_shape + 1, 0), sto(d->n_shape + 1, 0);
+    for (int64_t sh = 0; sh < d->n_shape; ++sh) {
+        const int N = d->shape_n_src[sh], M = d->shape_n_trg[sh];
+        if (N < 1 || M < N) return fail(MFS_EINVAL, "every shape needs 1 <= N <= M");
+        sso[sh + 1] = sso[sh] + N;
+        sto[sh + 1] = sto[sh] + M;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        if (d->shape_of_body[b] < 0 || d->shape_of_body[b] >= d->n_shape) return fail(MFS_EINVAL, "bad shape id");
+    for (int64_t q = 0; q < 3 * nb; ++q)
+        if (!std::isfinite(d->centre[q])) return fail(MFS_EINVAL, "non-finite centre");
+    for (int64_t q = 0; q < 9 * nb; ++q)
+        if (!std::isfinite(d->rot[q])) return fail(MFS_EINVAL, "non-finite rotation");
+
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<mfs_plan_s> p(new mfs_plan_s());
+    p->prec = d->precision;
+    p->mu = d->mu;
+    p->n_sys = d->n_sys;
+    p->n_body = nb;
+    p->sys_body_ptr.assign(d->sys_body_ptr, d->sys_body_ptr + d->n_sys + 1);
+    p->sys_kind.assign(d->sys_kind, d->sys_kind + d->n_sys);
+    p->kind.resize(nb);
+    p->n_src.resize(nb);
+    p->n_trg.resize(nb);
+    p->factor_of_body.resize(nb);
+    p->gam_off.resize(nb + 1);
+    p->lam_off.resize(nb + 1);
+    p->net_off.resize(nb + 1);
+    p->src_row.resize(nb + 1);
+    p->trg_row.resize(nb + 1);
+    p->gam_off[0] = p->lam_off[0] = p->net_off[0] = p->src_row[0] = p->trg_row[0] = 0;
+    std::vector<std::pair<int, int>> fkeys;
+    for (int64_t sy = 0; sy < d->n_sys; ++sy)
+        for (int64_t b = d->sys_body_ptr[sy]; b < d->sys_body_ptr[sy + 1]; ++b) {
+            const int k = d->sys_kind[sy], sh = d->shape_of_body[b];
+            const int dim = k == MFS_STOKES ? 3 : 1;
+            p->kind[b] = k;
+            p->n_src[b] = d->shape_n_src[sh];
+            p->n_trg[b] = d->shape_n_trg[sh];
+            p->gam_off[b + 1] = p->gam_off[b] + dim * p->n_trg[b];
+            p->lam_off[b + 1] = p->lam_off[b] + dim * p->n_src[b];
+            p->net_off[b + 1] = p->net_off[b] + (k == MFS_STOKES ? 6 : 1);
+            p->src_row[b + 1] = p->src_row[b] + p->n_src[b];
+            p->trg_row[b + 1] = p->trg_row[b] + p->n_trg[b];
+            auto key = std::make_pair(sh, k);
+            auto it = std::find(fkeys.begin(), fkeys.end(), key);
+            if (it == fkeys.end()) {
+                fkeys.push_back(key);
+                p->factor_of_body[b] = (int)fkeys.size() - 1;
+            } else {
+                p->factor_of_body[b] = (int)(it - fkeys.begin());
+            }
+        }
+    p->n_gamma = p->gam_off[nb];
+    p->n_lambda = p->lam_off[nb];
+    p->n_net = p->net_off[nb];
+    p->n_srcp = p->src_row[nb];
+    p->n_trgp = p->trg_row[nb];
+    if (p->n_srcp > INT32_MAX / 2 || p->n_trgp > INT32_MAX / 2) return fail(MFS_EINVAL, "too many points");
+    for (auto &k : fkeys) {
+        Factor F{};
+        F.shape = k.first;
+        F.kind = k.second;
+        const int dim = F.kind == MFS_STOKES ? 3 : 1;
+        F.dN = dim * d->shape_n_src[F.shape];
+        F.dM = dim * d->shape_n_trg[F.shape];
+        p->factors.push_back(F);
+    }
+    // host geometry: world-axis offsets of every point, Gram inverses per body
+    std::vector<double> so64(4 * p->n_srcp), to64(4 * p->n_trgp);
+    std::vector<float> so32(4 * p->n_srcp), to32(4 * p->n_trgp);
+    std::vector<double> gram(36 * nb, 0.0);
+    std::vector<int32_t> sbody(p->n_srcp), tbody(p->n_trgp);
+    std::vector<double> G0i_cache(36 * d->n_shape, 0.0);
+    std::vector<char> G0_ok(d->n_shape, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int sh = d->shape_of_body[b];
+        const double *R = d->rot + 9 * b;
+        auto emit = [&](const double *loc, int n, int64_t row0, std::vector<double> &o64, std::vector<float> &o32,
+                        std::vector<int32_t> &ids) {
+            for (int i = 0; i < n; ++i) {
+                const double *q = loc + 3 * i;
+                for (int a = 0; a < 3; ++a) {
+                    const double v = R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2];
+                    o64[4 * (row0 + i) + a] = v;
+                    o32[4 * (row0 + i) + a] = (float)v;
+                }
+                o64[4 * (row0 + i) + 3] = 0.0;
+                o32[4 * (row0 + i) + 3] = 0.f;
+                ids[row0 + i] = (int32_t)b;
+            }
+        };
+        emit(d->shape_src + 3 * sso[sh], p->n_src[b], p->src_row[b], so64, so32, sbody);
+        emit(d->shape_trg + 3 * sto[sh], p->n_trg[b], p->trg_row[b], to64, to32, tbody);
+        if (p->kind[b] == MFS_STOKES) {
+            if (!G0_ok[sh]) {
+                double G[36];
+                gram6(d->shape_src + 3 * sso[sh], p->n_src[b], G);
+                if (!inv6(G, &G0i_cache[36 * sh])) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
+                G0_ok[sh] = 1;
+            }
+            rotate_gram(&G0i_cache[36 * sh], R, &gram[36 * b]);
+        }
+    }
+    std::vector<int32_t> src_row32(p->src_row.begin(), p->src_row.end()), trg_row32(p->trg_row.begin(), p->trg_row.end());
+    std::vector<double> cen(d->centre, d->centre + 3 * nb), rot(d->rot, d->rot + 9 * nb);
+    MFS_TRY(upload_vec(p->d_kind, p->kind, s));
+    MFS_TRY(upload_vec(p->d_nsrc, p->n_src, s));
+    MFS_TRY(upload_vec(p->d_ntrg, p->n_trg, s));
+    MFS_TRY(upload_vec(p->d_gam_off, p->gam_off, s));
+    MFS_TRY(upload_vec(p->d_lam_off, p->lam_off, s));
+    MFS_TRY(upload_vec(p->d_net_off, p->net_off, s));
+    MFS_TRY(upload_vec(p->d_src_row32, src_row32, s));
+    MFS_TRY(upload_vec(p->d_trg_row32, trg_row32, s));
+    MFS_TRY(upload_vec(p->d_rot, rot, s));
+    MFS_TRY(upload_vec(p->d_gram_inv, gram, s));
+    MFS_TRY(upload_vec(p->d_centre, cen, s));
+    MFS_TRY(upload_vec(p->d_src_off64, so64, s));
+    MFS_TRY(upload_vec(p->d_trg_off64, to64, s));
+    MFS_TRY(upload_vec(p->d_src_off32, so32, s));
+    MFS_TRY(upload_vec(p->d_trg_off32, to32, s));
+    MFS_TRY(upload_vec(p->d_src_body, sbody, s));
+    MFS_TRY(upload_vec(p->d_trg_body, tbody, s));
+    // pair operand records: positions now, strengths written per call
+    {
+        std::vector<SrcS32> fs32(p->n_srcp);
+        std::vector<SrcL32> fl32(p->n_srcp);
+        std::vector<SrcS64> fs64(p->n_srcp);
+        std::vector<SrcL64> fl64(p->n_srcp);
+        for (int64_t j = 0; j < p->n_srcp; ++j) {
+            fs32[j].pos = make_float4(so32[4 * j], so32[4 * j + 1], so32[4 * j + 2], 0.f);
+            fs32[j].str = make_float4(0.f, 0.f, 0.f, 0.f);
+            fl32[j] = make_float4(so32[4 * j], so32[4 * j + 1], so32[4 * j + 2], 0.f);
+            fs64[j] = SrcS64{{so64[4 * j], so64[4 * j + 1], so64[4 * j + 2], 0.0}, {0.0, 0.0, 0.0, 0.0}};
+            fl64[j] = SrcL64{{so64[4 * j], so64[4 * j + 1], so64[4 * j + 2], 0.0}};
+        }
+        MFS_TRY(upload_vec(p->fS32, fs32, s));
+        MFS_TRY(upload_vec(p->fL32, fl32, s));
+        MFS_TRY(upload_vec(p->fS64, fs64, s));
+        MFS_TRY(upload_vec(p->fL64, fl64, s));
+        std::vector<SrcS32> ts32(p->n_trgp);
+        std::vector<SrcL32> tl32(p->n_trgp);
+        std::vector<SrcS64> ts64(p->n_trgp);
+        std::vector<SrcL64> tl64(p->n_trgp);
+        for (int64_t j = 0; j < p->n_trgp; ++j) {
+            ts32[j].pos = make_float4(to32[4 * j], to32[4 * j + 1], to32[4 * j + 2], 0.f);
+            ts32[j].str = make_float4(0.f, 0.f, 0.f, 0.f);
+            tl32[j] = make_float4(to32[4 * j], to32[4 * j + 1], to32[4 * j + 2], 0.f);
+            ts64[j] = SrcS64{{to64[4 * j], to64[4 * j + 1], to64[4 * j + 2], 0.0}, {0.0, 0.0, 0.0, 0.0}};
+            tl64[j] = SrcL64{{to64[4 * j], to64[4 * j + 1], to64[4 * j + 2], 0.0}};
+        }
+        MFS_TRY(upload_vec(p->tS32, ts32, s));
+        MFS_TRY(upload_vec(p->tL32, tl32, s));
+        MFS_TRY(upload_vec(p->tS64, ts64, s));
+        MFS_TRY(upload_vec(p->tL64, tl64, s));
+    }
+    // pair-sum items, forward (targets = collocation points) and transposed (targets = proxies)
+    {
+        std::vector<int64_t> src_row(p->src_row), trg_row(p->trg_row);
+        const int min_items = 2048;
+        MFS_TRY(build_p2p_items(p->p2p_fwd, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                                p->gam_off.data(), p->kind.data(), p->mu, 1, min_items, s));
+        MFS_TRY(build_p2p_items(p->p2p_tr, p->n_sys, p->sys_body_ptr.data(), src_row.data(), trg_row.data(),
+                                p->lam_off.data(), p->kind.data(), p->mu, 1, min_items, s));
+        MFS_TRY(build_p2p_items(p->p2p_fwd1, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                                p->gam_off.data(), p->kind.data(), p->mu, 1, min_items, s));
+        MFS_TRY(build_p2p_items(p->p2p_tr1, p->n_sys, p->sys_body_ptr.data(), src_row.data(), trg_row.data(),
+                                p->lam_off.data(), p->kind.data(), p->mu, 1, min_items, s));
+    }
+    // workspace
+    {
+        const int64_t ng = std::max<int64_t>(1, p->n_gamma), nl = std::max<int64_t>(1, p->n_lambda);
+        MFS_TRY(p->ws_g32.reserve(ng * sizeof(float)));
+        MFS_TRY(p->ws_l32a.reserve(nl * sizeof(float)));
+        MFS_TRY(p->ws_l32b.reserve(nl * sizeof(float)));
+        MFS_TRY(p->ws_g64.reserve(ng * sizeof(double)));
+        MFS_TRY(p->ws_l64a.reserve(nl * sizeof(double)));
+        MFS_TRY(p->ws_l64b.reserve(nl * sizeof(double)));
+        MFS_TRY(p->ws_l64c.reserve(nl * sizeof(double)));
+        const int ns = std::max({p->p2p_fwd.n_split, p->p2p_tr.n_split, p->p2p_fwd1.n_split, p->p2p_tr1.n_split});
+        const int64_t nv = std::max({ng, nl, 3 * p->n_srcp, 3 * p->n_trgp});
+        MFS_TRY(p->partial.reserve((size_t)(ns > 1 ? ns : 1) * nv * sizeof(double)));
+        MFS_TRY(p->sys_active.reserve(p->n_sys * sizeof(int32_t)));
+    }
+    MFS_TRY(factor_shapes(p.get(), d, sso, sto, s));
+    MFS_TRY(build_gemm_tables(p.get(), s));
+    // GMRES chunks (never straddle a system)
+    {
+        const int64_t CH = 4096;
+        p->h_sys_chunk_ptr.assign(1, 0);
+        for (int64_t sy = 0; sy < p->n_sys; ++sy) {
+            const int64_t a = p->gam_off[p->sys_body_ptr[sy]], e = p->gam_off[p->sys_body_ptr[sy + 1]];
+            for (int64_t c = a; c < e; c += CH) p->h_chunks.push_back(VecChunk{c, std::min(e, c + CH), (int32_t)sy, 0});
+            p->h_sys_chunk_ptr.push_back((int32_t)p->h_chunks.size());
+        }
+        MFS_TRY(upload_vec(p->chunks, p->h_chunks, s));
+        MFS_TRY(upload_vec(p->sys_chunk_ptr, p->h_sys_chunk_ptr, s));
+        MFS_TRY(p->flag.reserve(sizeof(int32_t)));
+    }
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    *out = p.release();
+    return MFS_OK;
+}
+
+int mfs_plan_sizes(mfs_plan p, int64_t *n_gamma, int64_t *n_lambda, int64_t *n_net, double *min_sigma_ratio) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (n_gamma) *n_gamma = p->n_gamma;
+    if (n_lambda) *n_lambda = p->n_lambda;
+    if (n_net) *n_net = p->n_net;
+    if (min_sigma_ratio) *min_sigma_ratio = p->min_ratio;
+    return MFS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// operator pieces
+// ---------------------------------------------------------------------------
+namespace {
+
+// out64 = (I - L)? R S_L^+ R^T in   (gamma layout in, lambda layout out), and/or the
+// strengths of the forward pair-sum records of precision src_prec (src_prec < 0: none).
+int precond_fwd(mfs_plan p, const double *in, int prec, bool project, double *out64, int src_prec, hipStream_t s) {
+    BodyView bv = p->view();
+    const bool f32 = prec == MFS_MIXED;
+    if (f32) {
+        MFS_TRY(launch_rotate_in(bv, in, p->ws_g32.ptr, true, false, s));
+        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd1.as<GemmGroup>(), p->A32.as<float>(),
+                                p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(), p->ws_l32a.as<float>(),
+                                p->d_col_lam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd2.as<GemmGroup>(), p->A32.as<float>(),
+                                p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(),
+                                p->d_col_lam.as<int64_t>(), s));
+    } else {
+        MFS_TRY(launch_rotate_in(bv, in, p->ws_g64.ptr, false, false, s));
+        MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd1.as<GemmGroup>(), p->A64.as<double>(),
+                                p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(), p->ws_l64a.as<double>(),
+                                p->d_col_lam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd2.as<GemmGroup>(), p->A64.as<double>(),
+                                p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(),
+                                p->d_col_lam.as<int64_t>(), s));
+    }
+    const void *lam = f32 ? (const void *)p->ws_l32b.ptr : (const void *)p->ws_l64b.ptr;
+    void *S = nullptr, *L = nullptr;
+    if (src_prec >= 0) {
+        S = src_prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr;
+        L = src_prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr;
+    }
+    return launch_project(bv, lam, f32, true, project, out64, S, L, src_prec < 0 ? 0 : src_prec, s);
+}
+
+// out (gamma layout) = R (S_L^+)^T R^T [(I - L)] in   (in: lambda layout, world)
+int precond_tr(mfs_plan p, const double *in, int prec, bool project, double *out, hipStream_t s) {
+    BodyView bv = p->view();
+    const double *src = in;
+    if (project) {
+        MFS_TRY(launch_project(bv, in, false, false, true, p->ws_l64c.as<double>(), nullptr, nullptr, 0, s));
+        src = p->ws_l64c.as<double>();
+    }
+    if (prec == MFS_MIXED) {
+        MFS_TRY(launch_rotate_in(bv, src, p->ws_l32a.ptr, true, true, s));
+        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_tr1.as<GemmGroup>(), p->A32.as<float>(),
+                                p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(),
+                                p->d_col_lam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f32(p->n_tiles_M, p->tiles_M.as<GemmTile>(), p->g_tr2.as<GemmGroup>(), p->A32.as<float>(),
+                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_g32.as<float>(),
+                                p->d_col_gam.as<int64_t>(), s));
+        return launch_rotate_out(bv, p->ws_g32.ptr, true, out, false, s);
+    }
+    MFS_TRY(launch_rotate_in(bv, src, p->ws_l64a.ptr, false, true, s));
+    MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_tr1.as<GemmGroup>(), p->A64.as<double>(),
+                            p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(),
+                            p->d_col_lam.as<int64_t>(), s));
+    MFS_TRY(launch_gemm_f64(p->n_tiles_M, p->tiles_M.as<GemmTile>(), p->g_tr2.as<GemmGroup>(), p->A64.as<double>(),
+                            p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_g64.as<double>(),
+                            p->d_col_gam.as<int64_t>(), s));
+    return launch_rotate_out(bv, p->ws_g64.ptr, false, out, false, s);
+}
+
+P2PLaunch fwd_launch(mfs_plan p, int prec) {
+    P2PLaunch L;
+    L.prec = prec;
+    L.centre = p->d_centre.as<double>();
+    L.trg_body = p->d_trg_body.as<int32_t>();
+    L.src_ptr = p->d_src_row32.as<int32_t>();
+    L.trg_off = prec == MFS_MIXED ? p->d_trg_off32.ptr : p->d_trg_off64.ptr;
+    L.srcS = prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr;
+    L.srcL = prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr;
+    L.partial = p->partial.as<double>();
+    L.n_val = p->n_gamma;
+    return L;
+}
+
+P2PLaunch tr_launch(mfs_plan p, int prec) {
+    P2PLaunch L;
+    L.prec = prec;
+    L.centre = p->d_centre.as<double>();
+    L.trg_body = p->d_src_body.as<int32_t>();
+    L.src_ptr = p->d_trg_row32.as<int32_t>();
+    L.trg_off = prec == MFS_MIXED ? p->d_src_off32.ptr : p->d_src_off64.ptr;
+    L.srcS = prec == MFS_MIXED ? p->tS32.ptr : p->tS64.ptr;
+    L.srcL = prec == MFS_MIXED ? p->tL32.ptr : p->tL64.ptr;
+    L.partial = p->partial.as<double>();
+    L.n_val = p->n_lambda;
+    return L;
+}
+
+// write strengths (gamma layout) into the transposed pair records (collocation points as sources)
+int set_tr_strength(mfs_plan p, const double *w, int prec, hipStream_t s) {
+    BodyView tv = p->view();
+    tv.n_src = tv.n_trg;
+    tv.lam_off = tv.gam_off;
+    tv.src_row = tv.trg_row;
+    return launch_set_src_strength(tv, w, prec == MFS_MIXED ? p->tS32.ptr : p->tS64.ptr,
+                                   prec == MFS_MIXED ? p->tL32.ptr : p->tL64.ptr, prec, s);
+}
+
+// write strengths (lambda layout) into the forward pair records
+int set_fwd_strength(mfs_plan p, const double *str, int prec, hipStream_t s) {
+    return launch_set_src_strength(p->view(), str, prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr,
+                                   prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr, prec, s);
+}
+
+int matvec_impl(mfs_plan p, const double *gamma, double *out, int prec, const int32_t *sys_active, hipStream_t s) {
+    MFS_TRY(precond_fwd(p, gamma, prec, true, nullptr, prec, s));
+    P2PLaunch L = fwd_launch(p, prec);
+    L.skip_same = true;
+    L.addend = gamma;
+    L.out = out;
+    L.sys_active = sys_active;
+    return launch_p2p(p->p2p_fwd, L, s);
+}
+
+// (A^T w)^(k') = w^(k') + R (S_L^+)^T R^T (I - L^(k')) sum_{k != k'} S^(kk')T w^(k)
+int matvec_adjoint_impl(mfs_plan p, const double *w, double *out, int prec, const int32_t *sys_active, hipStream_t s) {
+    MFS_TRY(set_tr_strength(p, w, prec, s));
+    P2PLaunch L = tr_launch(p, prec);
+    L.skip_same = true;
+    L.out = p->ws_l64c.as<double>();
+    L.sys_active = sys_active;
+    MFS_TRY(launch_p2p(p->p2p_tr, L, s));
+    MFS_TRY(launch_project(p->view(), p->ws_l64c.as<double>(), false, false, true, p->ws_l64c.as<double>(), nullptr,
+                           nullptr, 0, s));
+    MFS_TRY(precond_tr(p, p->ws_l64c.as<double>(), prec, false, out, s));
+    return launch_add_inplace(p->n_gamma, w, out, s);
+}
+
+int check_plan_prec(mfs_plan p, int prec) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    return check_prec(prec);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfs_rhs(mfs_plan p, const double *net, double *b, double *strength0, int prec, void *stream) {
+    MFS_TRY(check_plan_prec(p, prec));
+    if (!net || !b) return fail(MFS_EINVAL, "NULL net or b");
+    hipStream_t s = (hipStream_t)stream;
+    MFS_TRY(launch_completion(p->view(), net, strength0, prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr,
+                              prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr, prec, s));
+    P2PLaunch Lr = fwd_launch(p, prec);
+    Lr.skip_same = false;
+    Lr.alpha = -1.0;
+    Lr.out = b;
+    return launch_p2p(p->p2p_fwd, Lr, s);
+}
+
+int mfs_precond_apply(mfs_plan p, const double *in, double *out, int flags, int prec, void *stream) {
+    MFS_TRY(check_plan_prec(p, prec));
+    if (!in || !out) return fail(MFS_EINVAL, "NULL in or out");
+    if (flags & ~(MFS_PROJECT | MFS_TRANSPOSE)) return fail(MFS_EINVAL, "unknown flags");
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & MFS_TRANSPOSE) return precond_tr(p, in, prec, (flags & MFS_PROJECT) != 0, out, s);
+    return precond_fwd(p, in, prec, (flags & MFS_PROJECT) != 0, out, -1, s);
+}
+
+int mfs_matvec(mfs_plan p, const double *gamma, double *out, int prec, void *stream) {
+    MFS_TRY(check_plan_prec(p, prec));
+    if (!gamma || !out) return fail(MFS_EINVAL, "NULL gamma or out");
+    if (gamma == out) return fail(MFS_EINVAL, "gamma and out must not alias");
+    return matvec_impl(p, gamma, out, prec, nullptr, (hipStream_t)stream);
+}
+
+int mfs_matvec_adjoint(mfs_plan p, const double *w, double *out, int prec, void *stream) {
+    MFS_TRY(check_plan_prec(p, prec));
+    if (!w || !out) return fail(MFS_EINVAL, "NULL w or out");
+    if (w == out) return fail(MFS_EINVAL, "w and out must not alias");
+    return matvec_adjoint_impl(p, w, out, prec, nullptr, (hipStream_t)stream);
+}
+
+int mfs_extract(mfs_plan p, const double *gamma, const double *strength0, double *out, double *sigma, void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (!gamma || (!out && !sigma)) return fail(MFS_EINVAL, "NULL gamma or outputs");
+    hipStream_t s = (hipStream_t)stream;
+    MFS_TRY(precond_fwd(p, gamma, MFS_FP64, false, p->ws_l64c.as<double>(), -1, s));
+    return launch_extract(p->view(), p->ws_l64c.as<double>(), strength0, out, sigma, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// GMRES over the batch of systems
+// ---------------------------------------------------------------------------
+namespace {
+
+int ensure_krylov(mfs_plan p, int max_iter) {
+    if (p->gm_cap >= max_iter) return MFS_OK;
+    const int64_t n = std::max<int64_t>(1, p->n_gamma);
+    const int nc = (int)p->h_chunks.size();
+    const int S = (int)p->n_sys;
+    MFS_TRY(p->V.reserve((size_t)(max_iter + 1) * n * sizeof(double)));
+    MFS_TRY(p->Wv.reserve(n * sizeof(double)));
+    MFS_TRY(p->R.reserve(n * sizeof(double)));
+    MFS_TRY(p->X.reserve(n * sizeof(double)));
+    MFS_TRY(p->dots_partial.reserve((size_t)std::max(1, nc) * (max_iter + 2) * sizeof(double)));
+    MFS_TRY(p->dots.reserve((size_t)S * 2 * (max_iter + 2) * sizeof(double)));
+    MFS_TRY(p->nrm.reserve((size_t)S * sizeof(double)));
+    MFS_TRY(p->coef.reserve((size_t)S * (max_iter + 2) * sizeof(double)));
+    p->gm_cap = max_iter;
+    return MFS_OK;
+}
+
+// per-system squared norms of x -> host
+int sys_norms(mfs_plan p, const double *x, std::vector<double> &out, hipStream_t s) {
+    const int nc = (int)p->h_chunks.size();
+    const int ldp = p->gm_cap + 2;
+    MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), x, 0, 1, x, p->dots_partial.as<double>(), ldp, s));
+    MFS_TRY(launch_reduce_sys((int)p->n_sys, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
+                              p->nrm.as<double>(), 1, s));
+    out.resize(p->n_sys);
+    MFS_HIP_TRY(hipMemcpyAsync(out.data(), p->nrm.ptr, p->n_sys * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    for (auto &v : out) v = std::isnan(v) ? v : std::sqrt(std::max(0.0, v));  // keep NaN visible
+    return MFS_OK;
+}
+
+typedef int (*MatvecFn)(mfs_plan, const double *, double *, int, const int32_t *, hipStream_t);
+
+// One unrestarted GMRES attempt on A dx = r for every active system; x += dx.
+// target[s]: absolute residual target.  counts[s] += matvecs spent.  est[s]: final estimate.
+int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, const std::vector<double> &target,
+                  int max_iter, std::vector<int> &active, std::vector<int> &counts, std::vector<double> &est,
+                  hipStream_t s) {
+    const int S = (int)p->n_sys;
+    const int64_t n = p->n_gamma;
+    const int nc = (int)p->h_chunks.size();
+    const int ldp = p->gm_cap + 2;
+    const int ldh = p->gm_cap + 2;
+    double *V = p->V.as<double>();
+    double *w = p->Wv.as<double>();
+    std::vector<double> beta;
+    MFS_TRY(sys_norms(p, r, beta, s));
+    std::vector<int> act(S, 0);
+    int n_act = 0;
+    for (int sy = 0; sy < S; ++sy) {
+        act[sy] = active[sy] && beta[sy] > target[sy] && std::isfinite(beta[sy]);
+        if (active[sy] && !std::isfinite(beta[sy])) return fail(MFS_ENUMERIC, "non-finite residual");
+        est[sy] = beta[sy];
+        n_act += act[sy];
+    }
+    if (n_act == 0) return MFS_OK;
+    std::vector<double> scale(S);
+    for (int sy = 0; sy < S; ++sy) scale[sy] = act[sy] ? 1.0 / beta[sy] : 0.0;
+    MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+    MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), r, p->nrm.as<double>(), 1, V, s));
+    // Hessenberg columns and Givens data per system
+    std::vector<std::vector<double>> H(S, std::vector<double>((size_t)(max_iter + 1) * max_iter, 0.0));
+    std::vector<std::vector<double>> cs(S, std::vector<double>(max_iter)), sn(S, std::vector<double>(max_iter)),
+        g(S, std::vector<double>(max_iter + 1, 0.0));
+    std::vector<int> k(S, 0), live(act);
+    for (int sy = 0; sy < S; ++sy) g[sy][0] = beta[sy];
+    std::vector<int32_t> act32(S);
+    std::vector<double> hbuf((size_t)S * 2 * ldh), nrm(S);
+    for (int j = 0; j < max_iter; ++j) {
+        int any = 0;
+        for (int sy = 0; sy < S; ++sy) {
+            act32[sy] = live[sy];
+            any |= live[sy];
+        }
+        if (!any) break;
+        MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MFS_TRY(A(p, V + (int64_t)j * n, w, prec, p->sys_active.as<int32_t>(), s));
+        for (int sy = 0; sy < S; ++sy) counts[sy] += live[sy];
+        // classical Gram-Schmidt, twice
+        double *dots = p->dots.as<double>();
+        for (int pass = 0; pass < 2; ++pass) {
+            MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), V, n, j + 1, w, p->dots_partial.as<double>(), ldp, s));
+            MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, j + 1,
+                                      dots + pass * ldh, 2 * ldh, s));
+            MFS_TRY(launch_multi_axpy(nc, p->chunks.as<VecChunk>(), V, n, j + 1, dots + pass * ldh, 2 * ldh, -1.0, w, s));
+        }
+        MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), w, 0, 1, w, p->dots_partial.as<double>(), ldp, s));
+        MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
+                                  p->nrm.as<double>(), 1, s));
+        MFS_HIP_TRY(hipMemcpyAsync(hbuf.data(), dots, (size_t)S * 2 * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipMemcpyAsync(nrm.data(), p->nrm.ptr, S * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+        for (int sy = 0; sy < S; ++sy) {
+            scale[sy] = 0.0;
+            if (!live[sy]) continue;
+            double *h = &H[sy][(size_t)j * (max_iter + 1)];
+            for (int i = 0; i <= j; ++i) h[i] = hbuf[(size_t)sy * 2 * ldh + i] + hbuf[(size_t)sy * 2 * ldh + ldh + i];
+            const double hn = std::isnan(nrm[sy]) ? nrm[sy] : std::sqrt(std::max(0.0, nrm[sy]));
+            if (!std::isfinite(hn)) return fail(MFS_ENUMERIC, "non-finite Arnoldi vector");
+            h[j + 1] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[sy][i] * h[i] + sn[sy][i] * h[i + 1];
+                h[i + 1] = -sn[sy][i] * h[i] + cs[sy][i] * h[i + 1];
+                h[i] = t;
+            }
+            const double rho = std::hypot(h[j], h[j + 1]);
+            if (!(rho > 0.0)) {  // exact breakdown: the solution is in the current space
+                k[sy] = j;
+                live[sy] = 0;
+                continue;
+            }
+            cs[sy][j] = h[j] / rho;
+            sn[sy][j] = h[j + 1] / rho;
+            h[j] = rho;
+            h[j + 1] = 0.0;
+            g[sy][j + 1] = -sn[sy][j] * g[sy][j];
+            g[sy][j] = cs[sy][j] * g[sy][j];
+            k[sy] = j + 1;
+            est[sy] = std::fabs(g[sy][j + 1]);
+            if (est[sy] <= target[sy] || hn == 0.0) live[sy] = 0;
+            else scale[sy] = 1.0 / hn;
+        }
+        if (j + 1 < max_iter) {
+            MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+            MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, p->nrm.as<double>(), 1, V + (int64_t)(j + 1) * n, s));
+        }
+    }
+    // back substitution per system, x += V y
+    const int kmax = *std::max_element(k.begin(), k.end());
+    std::vector<double> y((size_t)S * ldh, 0.0);
+    for (int sy = 0; sy < S; ++sy) {
+        if (!act[sy]) continue;
+        const int kk = k[sy];
+        for (int i = kk - 1; i >= 0; --i) {
+            double t = g[sy][i];
+            for (int c = i + 1; c < kk; ++c) t -= H[sy][(size_t)c * (max_iter + 1) + i] * y[(size_t)sy * ldh + c];
+            y[(size_t)sy * ldh + i] = t / H[sy][(size_t)i * (max_iter + 1) + i];
+        }
+    }
+    if (kmax > 0) {
+        MFS_HIP_TRY(hipMemcpyAsync(p->coef.ptr, y.data(), (size_t)S * ldh * sizeof(double), hipMemcpyHostToDevice, s));
+        MFS_TRY(launch_multi_axpy(nc, p->chunks.as<VecChunk>(), V, n, kmax, p->coef.as<double>(), ldh, 1.0, x, s));
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return MFS_OK;
+}
+
+int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max_iter, int max_refine, bool adjoint,
+                     int32_t *iters, double *relres, hipStream_t s) {
+    MFS_TRY(ensure_krylov(p, max_iter));
+    MatvecFn A = adjoint ? matvec_adjoint_impl : matvec_impl;
+    const int S = (int)p->n_sys;
+    const int64_t n = p->n_gamma;
+    std::vector<double> bn;
+    MFS_TRY(sys_norms(p, b, bn, s));
+    for (int sy = 0; sy < S; ++sy)
+        if (!std::isfinite(bn[sy])) return fail(MFS_ENUMERIC, "non-finite right-hand side");
+    std::vector<double> target(S), est(S), rn(S);
+    std::vector<int> counts(S, 0), active(S, 1);
+    MFS_TRY(launch_fill(n, 0.0, x, s));
+    double *r = p->R.as<double>();
+    MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // mixed plans aim a little below tol so the FP64 check passes without a restart
+    const double inner = p->prec == MFS_MIXED ? 0.5 : 1.0;
+    for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
+    int status = MFS_OK;
+    if (p->prec == MFS_FP64) {
+        MFS_TRY(gmres_attempt(p, A, MFS_FP64, r, x, target, max_iter, active, counts, est, s));
+        for (int sy = 0; sy < S; ++sy) {
+            rn[sy] = est[sy];
+            if (!(est[sy] <= tol * bn[sy])) status = MFS_NOT_CONVERGED;
+        }
+    } else {
+        for (int attempt = 0; attempt <= max_refine; ++attempt) {
+            MFS_TRY(gmres_attempt(p, A, MFS_MIXED, r, x, target, max_iter, active, counts, est, s));
+            // true residual in FP64
+            std::vector<int32_t> act32(active.begin(), active.end());
+            MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            MFS_TRY(A(p, x, p->Wv.as<double>(), MFS_FP64, p->sys_active.as<int32_t>(), s));
+            for (int sy = 0; sy < S; ++sy) counts[sy] += active[sy];
+            MFS_TRY(launch_sub(n, b, p->Wv.as<double>(), r, s));
+            std::vector<double> tn;
+            MFS_TRY(sys_norms(p, r, tn, s));
+            bool all = true;
+            for (int sy = 0; sy < S; ++sy) {
+                if (!active[sy]) continue;
+                if (!std::isfinite(tn[sy])) return fail(MFS_ENUMERIC, "non-finite residual");
+                rn[sy] = tn[sy];
+                if (tn[sy] <= tol * bn[sy]) active[sy] = 0;
+                else all = false;
+            }
+            if (all) break;
+            // restart from x on the true residual: solve A dx = r
+            for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
+            // gmres_attempt adds into x directly
+        }
+        for (int sy = 0; sy < S; ++sy)
+            if (!(rn[sy] <= tol * bn[sy])) status = MFS_NOT_CONVERGED;
+    }
+    for (int sy = 0; sy < S; ++sy) {
+        if (iters) iters[sy] = counts[sy];
+        if (relres) relres[sy] = bn[sy] > 0 ? rn[sy] / bn[sy] : 0.0;
+    }
+    if (status == MFS_NOT_CONVERGED) set_error("GMRES: some system did not reach the tolerance");
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfs_gmres_solve(mfs_plan p, const double *b, double *gamma, double tol, int32_t max_iter, int32_t max_refine,
+                    int32_t adjoint, int32_t *iters, double *relres, void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (!b || !gamma) return fail(MFS_EINVAL, "NULL b or gamma");
+    if (b == gamma) return fail(MFS_EINVAL, "b and gamma must not alias");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFS_EINVAL, "tol must be finite and > 0");
+    if (max_iter < 1 || max_iter > 2000) return fail(MFS_EINVAL, "max_iter must be in [1, 2000]");
+    if (max_refine < 0 || max_refine > 100) return fail(MFS_EINVAL, "max_refine must be in [0, 100]");
+    return gmres_solve_impl(p, b, gamma, tol, max_iter, max_refine, adjoint != 0, iters, relres, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// gradient of J(out) with respect to the centres
+// ---------------------------------------------------------------------------
+extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double *strength0, const double *grad_out,
+                                  double *grad_centre, double tol, int32_t max_iter, int32_t max_refine, int32_t *iters,
+                                  double *relres, void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (!gamma || !grad_out || !grad_centre) return fail(MFS_EINVAL, "NULL gamma, grad_out or grad_centre");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFS_EINVAL, "tol must be finite and > 0");
+    if (max_iter < 1 || max_iter > 2000) return fail(MFS_EINVAL, "max_iter must be in [1, 2000]");
+    if (max_refine < 0 || max_refine > 100) return fail(MFS_EINVAL, "max_refine must be in [0, 100]");
+    hipStream_t s = (hipStream_t)stream;
+    const int prec = p->prec;
+    MFS_TRY(p->bw_sigma.reserve(std::max<int64_t>(1, p->n_lambda) * sizeof(double)));
+    MFS_TRY(p->bw_glam.reserve(std::max<int64_t>(1, p->n_lambda) * sizeof(double)));
+    MFS_TRY(p->bw_g.reserve(std::max<int64_t>(1, p->n_gamma) * sizeof(double)));
+    MFS_TRY(p->bw_w.reserve(std::max<int64_t>(1, p->n_gamma) * sizeof(double)));
+    MFS_TRY(p->bw_gt.reserve(std::max<int64_t>(1, 3 * p->n_trgp) * sizeof(double)));
+    MFS_TRY(p->bw_gs.reserve(std::max<int64_t>(1, 3 * p->n_srcp) * sizeof(double)));
+    BodyView bv = p->view();
+    // sigma = (I - L) S_L^+ gamma + s0 (FP64)
+    MFS_TRY(precond_fwd(p, gamma, MFS_FP64, false, p->ws_l64c.as<double>(), -1, s));
+    MFS_TRY(launch_extract(bv, p->ws_l64c.as<double>(), strength0, nullptr, p->bw_sigma.as<double>(), s));
+    // g = (S_L^+)^T dJ/dlambda
+    MFS_TRY(launch_grad_lambda(bv, grad_out, p->bw_glam.as<double>(), s));
+    MFS_TRY(precond_tr(p, p->bw_glam.as<double>(), MFS_FP64, false, p->bw_g.as<double>(), s));
+    // A^T w = g
+    int st = gmres_solve_impl(p, p->bw_g.as<double>(), p->bw_w.as<double>(), tol, max_iter, max_refine, true, iters,
+                              relres, s);
+    if (st < 0) return st;
+    // d(w^T R)/dx_i over off-body pairs (lanes: collocation points with w; sources: proxies with sigma)
+    MFS_TRY(set_fwd_strength(p, p->bw_sigma.as<double>(), prec, s));
+    P2PLaunch Lf = fwd_launch(p, prec);
+    Lf.skip_same = true;
+    Lf.alpha = -1.0;
+    Lf.out = p->bw_gt.as<double>();
+    Lf.n_val = 3 * p->n_trgp;
+    MFS_TRY(launch_p2p_grad(p->p2p_fwd1, Lf, p->bw_w.as<double>(), p->n_trgp, s));
+    // d(w^T R)/dy_j (lanes: proxies with sigma; sources: collocation points with w)
+    MFS_TRY(set_tr_strength(p, p->bw_w.as<double>(), prec, s));
+    P2PLaunch Lt = tr_launch(p, prec);
+    Lt.skip_same = true;
+    Lt.alpha = -1.0;
+    Lt.out = p->bw_gs.as<double>();
+    Lt.n_val = 3 * p->n_srcp;
+    MFS_TRY(launch_p2p_grad(p->p2p_tr1, Lt, p->bw_sigma.as<double>(), p->n_srcp, s));
+    MFS_TRY(launch_body_grad_reduce(p->n_body, p->d_trg_row32.as<int32_t>(), p->d_src_row32.as<int32_t>(),
+                                    p->bw_gt.as<double>(), p->bw_gs.as<double>(), grad_centre, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    return st;
+}

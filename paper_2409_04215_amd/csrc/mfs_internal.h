@@ -1,0 +1,209 @@
+// Internal declarations shared by the libmfs translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfs.h"
+
+namespace mfs {
+
+// ---------------------------------------------------------------------------
+// Error state
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+#define MFS_HIP_TRY(expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::mfs::fail(MFS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MFS_TRY(expr)          \
+    do {                       \
+        int s_ = (expr);       \
+        if (s_ < 0) return s_; \
+    } while (0)
+
+constexpr double PI = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Device buffer (library-owned memory)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    int reserve(size_t n);                 // grows (contents not kept)
+    int upload(const void *host, size_t n, hipStream_t s);
+    template <class T> T *as() const { return reinterpret_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------------------
+// Pair-sum operands.
+//
+// Coordinates are split as world = centre (FP64, per body) + offset, where the
+// offset (world axes, relative to the body centre) is small.  The mixed kernels
+// keep offsets and strengths in FP32 and form d = (float(c_t - c_s) + xt) - ys,
+// which keeps the FP32 rounding of d relative to |d| rather than to the
+// distance from the origin.
+// ---------------------------------------------------------------------------
+struct SrcS32 { float4 pos; float4 str; };   // Stokes mixed: offset, strength (w unused)
+struct SrcS64 { double pos[4]; double str[4]; };
+typedef float4 SrcL32;                         // Laplace mixed: offset xyz, strength w
+struct SrcL64 { double v[4]; };
+
+// One unit of pair-sum work: targets [t0, t1) of one system against the
+// sources of bodies [b0, b1) of the same system; results go to split slice
+// `split` at output offset out0 (+ dim per target).
+struct P2PItem {
+    int64_t out0;
+    double scale;        // 1/(4 pi) or 1/(8 pi mu)
+    int32_t t0, t1;
+    int32_t b0, b1;
+    int32_t sys;
+    int32_t split;
+    int32_t kind;
+    int32_t pad;
+};
+
+// Everything one pair-sum launch reads and writes (device pointers).
+struct P2PLaunch {
+    int prec = MFS_MIXED;
+    bool skip_same = true;
+    bool accumulate = false;
+    double alpha = 1.0;              // extra factor on the pair sum (e.g. -1 for b = -u0)
+    const double *centre = nullptr;  // [n_body][3] FP64 body centres
+    const int32_t *trg_body = nullptr;
+    const int32_t *src_ptr = nullptr;     // [n_body+1] source rows per body
+    const int32_t *sys_active = nullptr;  // [n_sys] or null
+    const void *trg_off = nullptr;        // float4 / double4 [n_trg] offsets from the body centre
+    const void *srcS = nullptr;           // SrcS32 / SrcS64 [n_src] (Stokes bodies)
+    const void *srcL = nullptr;           // SrcL32 / SrcL64 [n_src] (Laplace bodies)
+    double *out = nullptr;                // final output [n_val]
+    double *partial = nullptr;            // [n_split][n_val] when n_split > 1
+    const double *addend = nullptr;       // added once to the output (may be null)
+    int64_t n_val = 0;                    // output length
+};
+
+// Host-side description of a pair-sum launch.
+struct P2PPlan {
+    std::vector<P2PItem> items;
+    int n_split = 1;
+    int tpl = 1;
+    DevBuf d_items;
+};
+
+// items for targets grouped by body (body_trg_ptr), bodies grouped by system;
+// out_ptr[b] = output offset of body b's first target; dim_of_body 1 or 3.
+int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, const int64_t *out_ptr, const int32_t *kind_of_body,
+                    double mu, int tpl, int min_items, hipStream_t s);
+
+// kernels (p2p_kernels.hip)
+int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s);
+
+// Standalone conversion: FP64 world points to the split representation.
+int launch_body_refpoint(int64_t n_body, const int32_t *src_ptr, const int32_t *trg_ptr, const double *src_xyz,
+                         const double *trg_xyz, double *centre, hipStream_t s);
+int launch_make_trg_off(int64_t n_trg, const double *xyz, const int32_t *trg_body, const double *centre,
+                        int prec, void *out, hipStream_t s);
+int launch_make_src(int64_t n_src, int kind, const double *xyz, const int32_t *src_body, const double *centre,
+                    const double *str, int prec, void *out, hipStream_t s);
+int launch_fill_body_ids(int64_t n_body, const int32_t *ptr, int32_t *ids, hipStream_t s);
+
+// Position gradients of the pair sums (p2p_backward.hip): lane vectors indexed like the
+// forward output, gradient [n_lane][3].
+int launch_p2p_grad(const P2PPlan &pp, const P2PLaunch &L, const double *lane_vec, int64_t n_lane, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Block (one-body) kernels (block_kernels.hip)
+// ---------------------------------------------------------------------------
+struct GemmTile { int32_t group, m0, n0, pad; };
+struct GemmGroup {
+    int32_t M, K;             // A is M x K row-major (lda = K)
+    int32_t col_begin, ncol;  // columns [col_begin, col_begin+ncol) of the column table
+    int64_t a_off;            // element offset of A in the factor pool
+};
+
+int launch_gemm_f32(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const float *Apool,
+                    const float *B, const int64_t *b_col_off, float *C, const int64_t *c_col_off,
+                    hipStream_t s);
+int launch_gemm_f64(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const double *Apool,
+                    const double *B, const int64_t *b_col_off, double *C, const int64_t *c_col_off,
+                    hipStream_t s);
+
+// Per-body view used by rotation / projection / extraction kernels.
+struct BodyView {
+    int64_t n_body;
+    const int32_t *kind;       // [n_body]
+    const int32_t *n_src;      // [n_body]
+    const int32_t *n_trg;
+    const int64_t *gam_off;    // [n_body] offset in gamma layout
+    const int64_t *lam_off;    // [n_body] offset in lambda layout
+    const int64_t *net_off;    // [n_body] offset in net layout
+    const int32_t *src_row;    // [n_body] first source row (point index)
+    const int32_t *trg_row;
+    const double *rot;         // [n_body][9]
+    const double *gram_inv;    // [n_body][36] (Stokes bodies)
+    const double *src_off64;   // [n_src][4] world-axis offsets of the proxies
+};
+
+// in (world frame fp64) -> out (shape frame, float or double); gamma layout (M points per body)
+// or lambda layout (N points per body)
+int launch_rotate_in(const BodyView &bv, const double *in, void *out, bool out_f32, bool lam_layout, hipStream_t s);
+// shape frame (float or double) -> world frame fp64
+int launch_rotate_out(const BodyView &bv, const void *in, bool in_f32, double *out, bool lam_layout, hipStream_t s);
+// lam (lambda layout) -> optionally rotated to the world frame, optionally (I - L); written to out64
+// (may alias lam when lam is fp64 and rotate is false) and/or into the pair-sum source records
+// srcS / srcL (chosen by body kind; either may be null) of precision src_prec
+int launch_project(const BodyView &bv, const void *lam, bool lam_f32, bool rotate, bool project, double *out64,
+                   void *srcS, void *srcL, int src_prec, hipStream_t s);
+int launch_completion(const BodyView &bv, const double *net, double *s0, void *srcS, void *srcL, int src_prec,
+                      hipStream_t s);
+int launch_extract(const BodyView &bv, const double *lam, const double *s0, double *out, double *sigma,
+                   hipStream_t s);
+int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s);
+int launch_set_src_strength(const BodyView &bv, const double *str, void *srcS, void *srcL, int prec, hipStream_t s);
+int launch_body_grad_reduce(int64_t n_body, const int32_t *trg_ptr, const int32_t *src_ptr, const double *gt,
+                            const double *gs, double *grad_c, hipStream_t s);
+int launch_make_factor(int rows, int cols, const double *src, int64_t ld, bool transposed, const double *rs,
+                       const double *cs, double *d64, float *d32, hipStream_t s);
+
+// setup
+int launch_assemble_SL(int kind, int M, int N, const double *trg, const double *src, const double *gram_inv6,
+                       double mu, double *SL, double *work, hipStream_t s);
+int launch_scale_rows_to_f32(int rows, int cols, const double *src, int64_t ld_src, const double *row_scale,
+                             const double *col_scale, double *dst64, float *dst32, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Krylov vector kernels (krylov_kernels.hip)
+// ---------------------------------------------------------------------------
+struct VecChunk { int64_t begin, end; int32_t sys; int32_t pad; };
+int launch_multi_dot(int n_chunk, const VecChunk *chunks, const double *V, int64_t ldv, int nvec, const double *w,
+                     double *partial, int ld_partial, hipStream_t s);
+int launch_reduce_sys(int n_sys, const int32_t *sys_chunk_ptr, const double *partial, int ld_partial, int nval,
+                      double *out, int ld_out, hipStream_t s);
+int launch_multi_axpy(int n_chunk, const VecChunk *chunks, const double *V, int64_t ldv, int nvec,
+                      const double *coef, int ld_coef, double sign, double *w, hipStream_t s);
+int launch_scale_sys(int n_chunk, const VecChunk *chunks, const double *w, const double *scale, int ld_scale,
+                     double *out, hipStream_t s);
+int launch_sub(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+int launch_add_inplace(int64_t n, const double *a, double *out, hipStream_t s);
+int launch_fill(int64_t n, double v, double *out, hipStream_t s);
+int launch_check_finite(int64_t n, const double *x, int32_t *flag, hipStream_t s);
+
+}  // namespace mfs

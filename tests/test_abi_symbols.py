@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point include/mfs.h
+declares, and rejects bad arguments on the host before touching a GPU
+(CPU only: no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfs.h")
+LIB = os.path.join(ROOT, "paper_2409_04215_amd", "libmfs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libmfs.so is not built (run paper_2409_04215_amd/build.py)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("mfs_p2p_stokes", "mfs_p2p_laplace", "mfs_precond_apply", "mfs_matvec", "mfs_gmres_solve",
+                 "mfs_p2p_stokes_backward", "mfs_p2p_laplace_backward", "mfs_solve_backward"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_side_argument_errors(lib):
+    lib.mfs_last_error.restype = ctypes.c_char_p
+    i64 = ctypes.c_int64
+    p = ctypes.POINTER(ctypes.c_int64)
+    # n_sys < 1
+    st = lib.mfs_p2p_stokes(i64(0), None, None, None, None, None, None, None, ctypes.c_double(1.0), 1, 1, None)
+    assert st == -1 and b"n_sys" in lib.mfs_last_error()
+    # non-monotone system pointers
+    sp = (ctypes.c_int64 * 3)(0, 2, 1)
+    bp = (ctypes.c_int64 * 3)(0, 1, 2)
+    st = lib.mfs_p2p_laplace(i64(2), sp, bp, bp, None, None, None, None, 1, 1, None)
+    assert st == -1
+    # NULL plan everywhere
+    assert lib.mfs_plan_create(None, None, None) == -1
+    assert lib.mfs_matvec(None, None, None, 1, None) == -1
+    assert lib.mfs_gmres_solve(None, None, None, ctypes.c_double(1e-5), 10, 1, 0, None, None, None) == -1
+    assert lib.mfs_plan_destroy(None) == 0
