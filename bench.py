@@ -1,0 +1,208 @@
+"""Benchmark: one-body-preconditioned MFS mobility solve on one MI355X.
+
+A step is one whole solve of the hot path on a resident plan: completion
+strengths and right-hand side (pair sum over all pairs), GMRES on the square
+preconditioned system (each matvec = pseudo-inverse blocks on the matrix
+cores, FP64 rigid-body projection, off-body pair sum, + gamma), the FP64
+true-residual check, and recovery of the rigid velocities.  Inputs are
+resident in HBM before the timed region starts; the per-shape factorisation
+is setup and is timed separately.
+
+Printed JSON line (one):
+  value       - pair interactions evaluated per second over the timed steps
+                (off-body pairs x matvecs + all pairs of the right-hand side),
+                whole-job, mixed precision, in Ginteractions/s
+  roofline    - the dominant kernel (mixed Stokes pair sum): 28 flops per pair
+                x pairs per launch / average launch time from HIP events on
+                its own stream during the timed steps, against the FP32
+                vector peak
+  cpu_baseline- the FP64 CPU oracle on a bounded sample of the same workload
+  extra       - FP64 solve time on the GPU, speedup, iteration counts, ...
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = {1: 28.0, 0: 11.0}      # Stokes, Laplace (FMA = 2, rsqrt = 1)
+PEAK_FP32_TFLOPS = 157.3                  # MI355X FP32 vector peak (published)
+WORKLOADS = ("ellipsoids_100", "ellipsoids_1000")
+
+
+def _workload(name: str, kind: int):
+    import mfs_workloads as W
+    if name == "ellipsoids_100":
+        return W.ellipsoids_100(kind)
+    if name == "ellipsoids_1000":
+        return W.ellipsoids_1000(kind)
+    raise SystemExit(f"unknown workload {name}; choose from {WORKLOADS}")
+
+
+def _pairs(wl):
+    n_src = [wl.shapes[s].src.shape[0] for s in wl.shape_of_body]
+    n_trg = [wl.shapes[s].trg.shape[0] for s in wl.shape_of_body]
+    tot_src = sum(n_src)
+    off = sum(t * (tot_src - s) for t, s in zip(n_trg, n_src))
+    return float(off), float(sum(n_trg) * tot_src)
+
+
+def _timed_solves(plan, net, tol, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, res = [], []
+    for _ in range(steps):
+        out, info = plan.solve(net, tol=tol)
+        its.append(int(info["iters"][0]))
+        res.append(float(info["relres"][0]))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, its, res, out
+
+
+def cpu_baseline(wl, budget_s: float = 15.0):
+    """The oracle's matvec (FP64, plain C pair loops on all host threads plus
+    numpy pseudo-inverse blocks) on a sample of target rows; reports pairs/s."""
+    import numpy as np
+
+    import mfs_workloads as W
+    from oracle import mfs_oracle as O
+
+    pr = O.Problem.from_workload(wl)
+    g = W.random_vector(pr.n_gamma, 1)
+    n_src = pr.Y.shape[0]
+    rows_per_body = pr.bodies[0].X.shape[0]
+    rng = np.random.default_rng(0)
+    # calibrate on a small sample, then size the sample to the time budget
+    n_rows = 200
+    t0 = time.perf_counter()
+    pr.matvec(g, rows=np.sort(rng.choice(pr.X.shape[0], n_rows, replace=False)))
+    t_small = time.perf_counter() - t0
+    n_rows = int(min(pr.X.shape[0], max(200, n_rows * budget_s / max(t_small, 1e-3))))
+    rows = np.sort(rng.choice(pr.X.shape[0], n_rows, replace=False))
+    t0 = time.perf_counter()
+    pr.matvec(g, rows=rows)
+    dt = time.perf_counter() - t0
+    pairs = n_rows * (n_src - pr.bodies[0].Y.shape[0])
+    return dict(value=pairs / dt / 1e9, unit="Ginteractions/s", cores=O.oracle_threads(), kind="oracle",
+                sample=f"one FP64 oracle matvec of {wl.name} restricted to {n_rows} of {pr.X.shape[0]} "
+                       f"collocation rows (all {len(pr.bodies)} pseudo-inverse blocks + those rows' "
+                       f"off-body pair sums), {dt:.1f} s; pairs/s of that sample",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ellipsoids_100", choices=WORKLOADS)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2409_04215_amd import mfs
+
+    torch.cuda.set_device(0)
+    kind = 1  # Stokes mobility
+    wl = _workload(args.workload, kind)
+    off_pairs, all_pairs = _pairs(wl)
+    net = torch.tensor(np.concatenate([n.reshape(-1) for n in wl.net]), dtype=torch.float64, device="cuda")
+
+    t0 = time.perf_counter()
+    plan_mx = mfs.Plan.from_workload(wl, mfs.MIXED)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    plan_64 = mfs.Plan.from_workload(wl, mfs.FP64)
+
+    for _ in range(args.warmup):
+        plan_mx.solve(net, tol=args.tol)
+    plan_mx.set_timing(True)
+    plan_mx.timing(mfs.MIXED, reset=True)
+    plan_mx.timing(mfs.FP64, reset=True)
+    step_s, its, res, out_mx = _timed_solves(plan_mx, net, args.tol, args.steps, torch)
+    n_mx, ms_mx, ppl = plan_mx.timing(mfs.MIXED)
+    n_chk, ms_chk, _ = plan_mx.timing(mfs.FP64)
+    plan_mx.set_timing(False)
+    # pairs evaluated per step: every matvec (mixed and the FP64 residual checks) + the right-hand side
+    matvecs_per_step = (n_mx + n_chk) / args.steps
+    pairs_step = matvecs_per_step * off_pairs + all_pairs
+    value = pairs_step / step_s / 1e9
+
+    # FP64 reference solves on the GPU
+    plan_64.solve(net, tol=args.tol)
+    plan_64.set_timing(True)
+    fp64_s, its64, res64, out_64 = _timed_solves(plan_64, net, args.tol, args.fp64_steps, torch)
+    n64, ms64, _ = plan_64.timing(mfs.FP64)
+    plan_64.set_timing(False)
+    diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    avg_ms = ms_mx / max(n_mx, 1)
+    achieved = FLOPS_PER_PAIR[kind] * ppl / (avg_ms * 1e-3) / 1e12
+    avg64_ms = ms64 / max(n64, 1)
+    rec = {
+        "metric": "P2P Ginteractions/s + GMRES-to-1e-5 solve time, mixed vs FP64, 1 GPU",
+        "value": round(value, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pairs / f64 accumulation, projection and GMRES",
+        "data": "synthetic (seeded random ellipsoid suspension; the paper publishes no cluster files)",
+        "config": {"workload": args.workload, "bodies": wl.n_body, "proxies_per_body": 400,
+                   "collocation_per_body": 800, "kernel": "stokes mobility", "gmres_tol": args.tol,
+                   "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_pairs},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "p2p_mixed_kernel<1> (Stokes)", "avg_launch_ms": round(avg_ms, 4),
+                     "launches": n_mx, "flops_per_pair": FLOPS_PER_PAIR[kind], "pairs_per_launch": ppl},
+        "solve_time_mixed_s": round(step_s, 5),
+        "solve_time_fp64_s": round(fp64_s, 5),
+        "speedup_mixed_vs_fp64": round(fp64_s / step_s, 3),
+        "matvecs_per_solve_mixed": matvecs_per_step,
+        "fp64_check_matvecs_per_solve": n_chk / args.steps,
+        "matvecs_per_solve_fp64": n64 / max(args.fp64_steps, 1),
+        "relres_mixed_true_fp64": res[-1],
+        "relres_fp64": res64[-1],
+        "p2p_kernel_ginter_s_mixed": round(ppl / (avg_ms * 1e-3) / 1e9, 2),
+        "p2p_kernel_ginter_s_fp64": round(ppl / (avg64_ms * 1e-3) / 1e9, 2) if n64 else None,
+        "rel_diff_U_mixed_vs_fp64_gpu": diff,
+        "setup_s": round(setup_s, 3),
+    }
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -225,6 +225,16 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
                        double *grad_centre, double tol, int32_t max_iter, int32_t max_refine,
                        int32_t *iters, double *relres, void *stream);
 
+/* Instrumentation.  With timing enabled, every pair-sum launch of the plan's
+ * matvec (the dominant kernel) is bracketed by HIP events recorded on the
+ * call's stream, directly before and after the kernel.  mfs_plan_timing
+ * returns, for precision prec, the number of timed launches, their summed
+ * kernel time in ms (synchronises on the last recorded event) and the number
+ * of off-body pairs one launch evaluates; reset != 0 clears the counters. */
+int mfs_plan_set_timing(mfs_plan plan, int32_t enable);
+int mfs_plan_timing(mfs_plan plan, int32_t prec, int32_t reset, int64_t *launches, double *total_ms,
+                    double *pairs_per_launch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,105 +22,145 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
-
 // ---------------------------------------------------------------------------
 // Grouped GEMM: C[:, col] = A_g * B[:, col] for every column of every group.
-// A_g row-major (M x K, lda = K) in a pool; B and C columns are contiguous
-// vectors at per-column element offsets.
+// A_g row-major (M x K, lda = K) in a factor pool; B and C columns are
+// contiguous vectors at per-column element offsets.
+//
+// One wave computes one 32 x 32 output tile over a K range.  Fragments are
+// loaded straight from global memory into registers (no LDS): the order in
+// which the K index is visited is permuted per lane so that every lane reads
+// contiguous runs of its own A row and B column (any bijection of K that A
+// and B share leaves the product unchanged).
+//  * f32, v_mfma_f32_32x32x2f32: lane l holds A[l%32][k] and B[k][l%32];
+//    lanes 0-31 walk k in [k0, k0+32), lanes 32-63 in [k0+32, k0+64).
+//  * f64, v_mfma_f64_16x16x4f64 (2 x 2 blocks of 16 x 16): lane l holds
+//    A[l%16][k] and B[k][l%16]; lane group l/16 walks 16 consecutive k.
+// A K range is split across waves when there are few output tiles; split
+// slices land in a partial buffer that a second kernel sums in a fixed order.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmTile *__restrict__ tiles,
-                                                   const GemmGroup *__restrict__ groups,
-                                                   const T *__restrict__ Apool, const T *__restrict__ B,
-                                                   const int64_t *__restrict__ b_col_off, T *__restrict__ C,
-                                                   const int64_t *__restrict__ c_col_off) {
-    __shared__ T As[BM][BK + 1];
-    __shared__ T Bs[BN][BK + 1];
-    const GemmTile tl = tiles[blockIdx.x];
-    const GemmGroup g = groups[tl.group];
-    const T *A = Apool + g.a_off;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+constexpr int KT = 64;  // K per register tile
 
-    // loader mapping: thread -> (row/col r, 4 consecutive k)
-    const int lr = tid >> 2, lk = (tid & 3) * 4;
-    const int arow = tl.m0 + lr;
-    const int bcol = tl.n0 + lr;
-    const bool a_ok = arow < g.M;
-    const bool b_ok = bcol < g.ncol;
-    const T *a_ptr = A + (int64_t)(a_ok ? arow : 0) * g.K;
-    const T *b_ptr = B + b_col_off[g.col_begin + (b_ok ? bcol : 0)];
-
-    if constexpr (sizeof(T) == 4) {
-        floatx16 acc = {};
-        for (int k0 = 0; k0 < g.K; k0 += BK) {
+template <class T, int N>
+__device__ __forceinline__ void load_run(const T *__restrict__ p, int k, int K, bool ok, bool vec, T (&v)[N]) {
+    // v[t] = p[k + t] for k + t < K (else 0); p is a row or column start
+    if (ok && vec && k + N <= K) {
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = k0 + lk + q;
-                As[lr][lk + q] = (a_ok && k < g.K) ? a_ptr[k] : T(0);
-                Bs[lr][lk + q] = (b_ok && k < g.K) ? b_ptr[k] : T(0);
+            for (int t = 0; t < N; t += 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(p + k + t);
+                v[t] = q.x; v[t + 1] = q.y; v[t + 2] = q.z; v[t + 3] = q.w;
             }
-            __syncthreads();
+        } else {
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 2) {
-                const float a = As[wm * 32 + (lane & 31)][kk + (lane >> 5)];
-                const float b = Bs[wn * 32 + (lane & 31)][kk + (lane >> 5)];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-            }
-            __syncthreads();
-        }
-        // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
-        const int col = tl.n0 + wn * 32 + (lane & 31);
-        if (col < g.ncol) {
-            T *c_ptr = C + c_col_off[g.col_begin + col];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = tl.m0 + wm * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                if (row < g.M) c_ptr[row] = acc[r];
+            for (int t = 0; t < N; t += 2) {
+                const double2 q = *reinterpret_cast<const double2 *>(p + k + t);
+                v[t] = q.x; v[t + 1] = q.y;
             }
         }
     } else {
+#pragma unroll
+        for (int t = 0; t < N; ++t) v[t] = (ok && k + t < K) ? p[k + t] : T(0);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, const GemmTile *__restrict__ tiles,
+                                                   const GemmGroup *__restrict__ groups, const T *__restrict__ Apool,
+                                                   const T *__restrict__ B, const int64_t *__restrict__ b_col_off,
+                                                   T *__restrict__ C, const int64_t *__restrict__ c_col_off,
+                                                   T *__restrict__ partial, int64_t part_col_stride,
+                                                   int64_t part_split_stride, int vec_ok) {
+    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= n_tiles) return;
+    const GemmTile tl = tiles[task];
+    const GemmGroup g = groups[tl.group];
+    const T *A = Apool + g.a_off;
+    const int lane = threadIdx.x & 63;
+    const bool vec = vec_ok && (g.K % (sizeof(T) == 4 ? 4 : 2)) == 0;
+    if constexpr (sizeof(T) == 4) {
+        const int i = tl.m0 + (lane & 31), j = tl.n0 + (lane & 31), h = lane >> 5;
+        const bool a_ok = i < g.M, b_ok = j < g.ncol;
+        const T *arow = A + (int64_t)(a_ok ? i : 0) * g.K;
+        const T *bcol = B + b_col_off[g.col_begin + (b_ok ? j : 0)];
+        floatx16 acc = {};
+        for (int k0 = tl.k0; k0 < tl.k1; k0 += KT) {
+            float av[32], bv[32];
+            load_run<float, 32>(arow, k0 + 32 * h, tl.k1, a_ok, vec, av);
+            load_run<float, 32>(bcol, k0 + 32 * h, tl.k1, b_ok, vec, bv);
+#pragma unroll
+            for (int t = 0; t < 32; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
+        }
+        // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
+        const int col = tl.n0 + (lane & 31);
+        if (col < g.ncol) {
+            T *out = partial ? partial + tl.split * part_split_stride + (int64_t)(g.col_begin + col) * part_col_stride
+                             : C + c_col_off[g.col_begin + col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = tl.m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                if (row < g.M) out[row] = acc[r];
+            }
+        }
+    } else {
+        const int q = lane >> 4, c16 = lane & 15;
+        const T *arow[2];
+        const T *bcol[2];
+        bool a_ok[2], b_ok[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = tl.m0 + 16 * u + c16, j = tl.n0 + 16 * u + c16;
+            a_ok[u] = i < g.M;
+            b_ok[u] = j < g.ncol;
+            arow[u] = A + (int64_t)(a_ok[u] ? i : 0) * g.K;
+            bcol[u] = B + b_col_off[g.col_begin + (b_ok[u] ? j : 0)];
+        }
         doublex4 acc[2][2] = {};
-        for (int k0 = 0; k0 < g.K; k0 += BK) {
+        for (int k0 = tl.k0; k0 < tl.k1; k0 += KT) {
+            double av[2][16], bv[2][16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = k0 + lk + q;
-                As[lr][lk + q] = (a_ok && k < g.K) ? a_ptr[k] : T(0);
-                Bs[lr][lk + q] = (b_ok && k < g.K) ? b_ptr[k] : T(0);
+            for (int u = 0; u < 2; ++u) {
+                load_run<double, 16>(arow[u], k0 + 16 * q, tl.k1, a_ok[u], vec, av[u]);
+                load_run<double, 16>(bcol[u], k0 + 16 * q, tl.k1, b_ok[u], vec, bv[u]);
             }
-            __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
+            for (int t = 0; t < 16; ++t)
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const double a = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const double b = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i][j], 0, 0, 0);
-                    }
-                }
-            }
-            __syncthreads();
+                    for (int w = 0; w < 2; ++w)
+                        acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[w][t], acc[u][w], 0, 0, 0);
         }
         // D layout (16x16x4 f64, measured on gfx950): lane l, reg r -> row l/16 + 4 r, col l%16
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = tl.n0 + wn * 32 + j * 16 + (lane & 15);
+        for (int w = 0; w < 2; ++w) {
+            const int col = tl.n0 + 16 * w + c16;
             if (col >= g.ncol) continue;
-            T *c_ptr = C + c_col_off[g.col_begin + col];
+            T *out = partial ? partial + tl.split * part_split_stride + (int64_t)(g.col_begin + col) * part_col_stride
+                             : C + c_col_off[g.col_begin + col];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = tl.m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
-                    if (row < g.M) c_ptr[row] = acc[i][j][r];
+                    const int row = tl.m0 + 16 * u + q + 4 * r;
+                    if (row < g.M) out[row] = acc[u][w][r];
                 }
-            }
         }
+    }
+}
+
+// C[:, col] = sum over split slices (fixed order); one block per column
+template <class T>
+__global__ void gemm_reduce_kernel(const int32_t *__restrict__ col_group, const GemmGroup *__restrict__ groups,
+                                   const T *__restrict__ partial, int64_t part_col_stride, int64_t part_split_stride,
+                                   int n_split, T *__restrict__ C, const int64_t *__restrict__ c_col_off) {
+    const int col = blockIdx.x;
+    const int M = groups[col_group[col]].M;
+    T *out = C + c_col_off[col];
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        T s = 0;
+        for (int sp = 0; sp < n_split; ++sp) s += partial[sp * part_split_stride + (int64_t)col * part_col_stride + m];
+        out[m] = s;
     }
 }
 
@@ -543,19 +583,33 @@ __global__ void make_factor_kernel(int rows, int cols, const double *__restrict_
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-int launch_gemm_f32(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const float *Apool, const float *B,
-                    const int64_t *b_col_off, float *C, const int64_t *c_col_off, hipStream_t s) {
-    if (n_tiles == 0) return MFS_OK;
-    gemm_kernel<float><<<n_tiles, 256, 0, s>>>(tiles, groups, Apool, B, b_col_off, C, c_col_off);
+int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, const int64_t *b_col_off, float *C,
+                    const int64_t *c_col_off, float *partial, hipStream_t s) {
+    if (G.n_tiles == 0) return MFS_OK;
+    float *part = G.n_split > 1 ? partial : nullptr;
+    gemm_kernel<float><<<(G.n_tiles + 3) / 4, 256, 0, s>>>(G.n_tiles, G.tiles, G.groups, Apool, B, b_col_off, C,
+                                                          c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
+    if (part) {
+        gemm_reduce_kernel<float><<<G.n_cols, 256, 0, s>>>(G.col_group, G.groups, part, G.part_col_stride,
+                                                           G.part_split_stride, G.n_split, C, c_col_off);
+        MFS_HIP_TRY(hipGetLastError());
+    }
     return MFS_OK;
 }
 
-int launch_gemm_f64(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const double *Apool,
-                    const double *B, const int64_t *b_col_off, double *C, const int64_t *c_col_off, hipStream_t s) {
-    if (n_tiles == 0) return MFS_OK;
-    gemm_kernel<double><<<n_tiles, 256, 0, s>>>(tiles, groups, Apool, B, b_col_off, C, c_col_off);
+int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, const int64_t *b_col_off, double *C,
+                    const int64_t *c_col_off, double *partial, hipStream_t s) {
+    if (G.n_tiles == 0) return MFS_OK;
+    double *part = G.n_split > 1 ? partial : nullptr;
+    gemm_kernel<double><<<(G.n_tiles + 3) / 4, 256, 0, s>>>(G.n_tiles, G.tiles, G.groups, Apool, B, b_col_off, C,
+                                                            c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
+    if (part) {
+        gemm_reduce_kernel<double><<<G.n_cols, 256, 0, s>>>(G.col_group, G.groups, part, G.part_col_stride,
+                                                            G.part_split_stride, G.n_split, C, c_col_off);
+        MFS_HIP_TRY(hipGetLastError());
+    }
     return MFS_OK;
 }
 

@@ -331,8 +331,12 @@ struct mfs_plan_s {
     DevBuf A32, A64;
     std::vector<Factor> factors;
     DevBuf d_col_gam, d_col_lam;
-    DevBuf g_fwd1, g_fwd2, g_tr1, g_tr2, tiles_N, tiles_M;
-    int n_tiles_N = 0, n_tiles_M = 0;
+    // grouped GEMMs: forward U^T then W; transposed W^T then U
+    struct GemmTables {
+        DevBuf groups, tiles, col_group;
+        GemmLaunch L;
+    } gm[4];
+    DevBuf gpart32, gpart64;
     // pair plans
     P2PPlan p2p_fwd, p2p_tr, p2p_fwd1, p2p_tr1;  // *1: one target per lane (gradient kernels)
     // workspace
@@ -342,6 +346,20 @@ struct mfs_plan_s {
     DevBuf V, Wv, R, X, dots_partial, dots, nrm, coef, chunks, sys_chunk_ptr, flag;
     // backward
     DevBuf bw_sigma, bw_glam, bw_g, bw_w, bw_gt, bw_gs;
+    // optional timing of the matvec pair-sum kernel (per precision)
+    struct Timer {
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        int used = 0;
+        int64_t launches = 0;
+        double total_ms = 0.0;
+    } timer[2];
+    bool timing = false;
+    double offbody_pairs = 0.0;
+
+    ~mfs_plan_s() {
+        for (auto &t : timer)
+            for (auto e : t.ev) (void)hipEventDestroy(e);
+    }
     std::vector<VecChunk> h_chunks;
     std::vector<int32_t> h_sys_chunk_ptr;
 
@@ -429,39 +447,79 @@ void rotate_gram(const double *G0i, const double *R, double *Gi) {
         }
 }
 
+// Work tables of one grouped GEMM: tiles of 32 x 32 outputs, K split into
+// n_split ranges when there are too few tiles to fill the device.
+int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &groups,
+                      const std::vector<int32_t> &col_group, const std::vector<int64_t> &b_col_off, hipStream_t s) {
+    int64_t tiles32 = 0, kmax = 0, mmax = 0;
+    for (auto &g : groups) {
+        tiles32 += (int64_t)((g.M + 31) / 32) * ((g.ncol + 31) / 32);
+        kmax = std::max<int64_t>(kmax, g.K);
+        mmax = std::max<int64_t>(mmax, g.M);
+    }
+    const int64_t target = 2048;
+    int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((target + tiles32 - 1) / tiles32, (kmax + 255) / 256));
+    std::vector<GemmTile> tiles;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const GemmGroup &g = groups[gi];
+        const int kchunk = (int)(((g.K + n_split - 1) / n_split + 63) / 64 * 64);
+        for (int m0 = 0; m0 < g.M; m0 += 32)
+            for (int n0 = 0; n0 < g.ncol; n0 += 32)
+                for (int sp = 0; sp < n_split; ++sp) {
+                    const int k0 = std::min(g.K, sp * kchunk), k1 = std::min(g.K, k0 + kchunk);
+                    tiles.push_back(GemmTile{(int32_t)gi, m0, n0, k0, k1, sp});
+                }
+    }
+    MFS_TRY(upload_vec(T.groups, groups, s));
+    MFS_TRY(upload_vec(T.tiles, tiles, s));
+    MFS_TRY(upload_vec(T.col_group, col_group, s));
+    T.L.n_tiles = (int)tiles.size();
+    T.L.n_split = n_split;
+    T.L.n_cols = (int)col_group.size();
+    T.L.tiles = T.tiles.as<GemmTile>();
+    T.L.groups = T.groups.as<GemmGroup>();
+    T.L.col_group = T.col_group.as<int32_t>();
+    T.L.part_col_stride = mmax;
+    T.L.part_split_stride = mmax * (int64_t)col_group.size();
+    // 16-byte alignment of every A row and B column start (float offsets % 4; doubles only need % 2)
+    bool al = true;
+    for (auto &g : groups) al = al && g.a_off % 4 == 0 && g.K % 4 == 0;
+    for (int64_t o : b_col_off) al = al && o % 4 == 0;
+    T.L.vec4 = al ? 1 : 0;
+    return MFS_OK;
+}
+
 int build_gemm_tables(mfs_plan p, hipStream_t s) {
     // groups: per factor, the list of its bodies as columns
     std::vector<std::vector<int32_t>> cols(p->factors.size());
     for (int64_t b = 0; b < p->n_body; ++b) cols[p->factor_of_body[b]].push_back((int32_t)b);
     std::vector<int64_t> col_gam, col_lam;
+    std::vector<int32_t> col_group;
     std::vector<GemmGroup> g1, g2, t1, t2;
-    std::vector<GemmTile> tiN, tiM;
     for (size_t f = 0; f < p->factors.size(); ++f) {
         const Factor &F = p->factors[f];
         const int32_t cb = (int32_t)col_gam.size(), nc = (int32_t)cols[f].size();
         for (int32_t b : cols[f]) {
             col_gam.push_back(p->gam_off[b]);
             col_lam.push_back(p->lam_off[b]);
+            col_group.push_back((int32_t)f);
         }
         g1.push_back(GemmGroup{F.dN, F.dM, cb, nc, F.ut_off});
         g2.push_back(GemmGroup{F.dN, F.dN, cb, nc, F.w_off});
         t1.push_back(GemmGroup{F.dN, F.dN, cb, nc, F.wt_off});
         t2.push_back(GemmGroup{F.dM, F.dN, cb, nc, F.u_off});
-        for (int m0 = 0; m0 < F.dN; m0 += 64)
-            for (int n0 = 0; n0 < nc; n0 += 64) tiN.push_back(GemmTile{(int32_t)f, m0, n0, 0});
-        for (int m0 = 0; m0 < F.dM; m0 += 64)
-            for (int n0 = 0; n0 < nc; n0 += 64) tiM.push_back(GemmTile{(int32_t)f, m0, n0, 0});
     }
     MFS_TRY(upload_vec(p->d_col_gam, col_gam, s));
     MFS_TRY(upload_vec(p->d_col_lam, col_lam, s));
-    MFS_TRY(upload_vec(p->g_fwd1, g1, s));
-    MFS_TRY(upload_vec(p->g_fwd2, g2, s));
-    MFS_TRY(upload_vec(p->g_tr1, t1, s));
-    MFS_TRY(upload_vec(p->g_tr2, t2, s));
-    MFS_TRY(upload_vec(p->tiles_N, tiN, s));
-    MFS_TRY(upload_vec(p->tiles_M, tiM, s));
-    p->n_tiles_N = (int)tiN.size();
-    p->n_tiles_M = (int)tiM.size();
+    MFS_TRY(build_gemm_launch(p->gm[0], g1, col_group, col_gam, s));
+    MFS_TRY(build_gemm_launch(p->gm[1], g2, col_group, col_lam, s));
+    MFS_TRY(build_gemm_launch(p->gm[2], t1, col_group, col_lam, s));
+    MFS_TRY(build_gemm_launch(p->gm[3], t2, col_group, col_lam, s));
+    int64_t part = 1;
+    for (auto &T : p->gm)
+        if (T.L.n_split > 1) part = std::max<int64_t>(part, T.L.n_split * T.L.part_split_stride);
+    MFS_TRY(p->gpart32.reserve(part * sizeof(float)));
+    MFS_TRY(p->gpart64.reserve(part * sizeof(double)));
     return MFS_OK;
 }
 
@@ -791,6 +849,11 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     }
     MFS_TRY(factor_shapes(p.get(), d, sso, sto, s));
     MFS_TRY(build_gemm_tables(p.get(), s));
+    for (int64_t sy = 0; sy < p->n_sys; ++sy) {
+        const int64_t b0 = p->sys_body_ptr[sy], b1 = p->sys_body_ptr[sy + 1];
+        const double ns = (double)(p->src_row[b1] - p->src_row[b0]);
+        for (int64_t b = b0; b < b1; ++b) p->offbody_pairs += (double)p->n_trg[b] * (ns - p->n_src[b]);
+    }
     // GMRES chunks (never straddle a system)
     {
         const int64_t CH = 4096;
@@ -832,20 +895,16 @@ int precond_fwd(mfs_plan p, const double *in, int prec, bool project, double *ou
     const bool f32 = prec == MFS_MIXED;
     if (f32) {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g32.ptr, true, false, s));
-        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd1.as<GemmGroup>(), p->A32.as<float>(),
-                                p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(), p->ws_l32a.as<float>(),
-                                p->d_col_lam.as<int64_t>(), s));
-        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd2.as<GemmGroup>(), p->A32.as<float>(),
-                                p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(),
-                                p->d_col_lam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f32(p->gm[0].L, p->A32.as<float>(), p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(),
+                                p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
+        MFS_TRY(launch_gemm_f32(p->gm[1].L, p->A32.as<float>(), p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(),
+                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
     } else {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g64.ptr, false, false, s));
-        MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd1.as<GemmGroup>(), p->A64.as<double>(),
-                                p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(), p->ws_l64a.as<double>(),
-                                p->d_col_lam.as<int64_t>(), s));
-        MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_fwd2.as<GemmGroup>(), p->A64.as<double>(),
-                                p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(),
-                                p->d_col_lam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f64(p->gm[0].L, p->A64.as<double>(), p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(),
+                                p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s));
+        MFS_TRY(launch_gemm_f64(p->gm[1].L, p->A64.as<double>(), p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(),
+                                p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s));
     }
     const void *lam = f32 ? (const void *)p->ws_l32b.ptr : (const void *)p->ws_l64b.ptr;
     void *S = nullptr, *L = nullptr;
@@ -866,21 +925,17 @@ int precond_tr(mfs_plan p, const double *in, int prec, bool project, double *out
     }
     if (prec == MFS_MIXED) {
         MFS_TRY(launch_rotate_in(bv, src, p->ws_l32a.ptr, true, true, s));
-        MFS_TRY(launch_gemm_f32(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_tr1.as<GemmGroup>(), p->A32.as<float>(),
-                                p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(),
-                                p->d_col_lam.as<int64_t>(), s));
-        MFS_TRY(launch_gemm_f32(p->n_tiles_M, p->tiles_M.as<GemmTile>(), p->g_tr2.as<GemmGroup>(), p->A32.as<float>(),
-                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->ws_g32.as<float>(),
-                                p->d_col_gam.as<int64_t>(), s));
+        MFS_TRY(launch_gemm_f32(p->gm[2].L, p->A32.as<float>(), p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(),
+                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
+        MFS_TRY(launch_gemm_f32(p->gm[3].L, p->A32.as<float>(), p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(),
+                                p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(), p->gpart32.as<float>(), s));
         return launch_rotate_out(bv, p->ws_g32.ptr, true, out, false, s);
     }
     MFS_TRY(launch_rotate_in(bv, src, p->ws_l64a.ptr, false, true, s));
-    MFS_TRY(launch_gemm_f64(p->n_tiles_N, p->tiles_N.as<GemmTile>(), p->g_tr1.as<GemmGroup>(), p->A64.as<double>(),
-                            p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(),
-                            p->d_col_lam.as<int64_t>(), s));
-    MFS_TRY(launch_gemm_f64(p->n_tiles_M, p->tiles_M.as<GemmTile>(), p->g_tr2.as<GemmGroup>(), p->A64.as<double>(),
-                            p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->ws_g64.as<double>(),
-                            p->d_col_gam.as<int64_t>(), s));
+    MFS_TRY(launch_gemm_f64(p->gm[2].L, p->A64.as<double>(), p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(),
+                            p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s));
+    MFS_TRY(launch_gemm_f64(p->gm[3].L, p->A64.as<double>(), p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(),
+                            p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(), p->gpart64.as<double>(), s));
     return launch_rotate_out(bv, p->ws_g64.ptr, false, out, false, s);
 }
 
@@ -928,6 +983,21 @@ int set_fwd_strength(mfs_plan p, const double *str, int prec, hipStream_t s) {
                                    prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr, prec, s);
 }
 
+// Collects the elapsed times of the recorded event pairs of one precision.
+int harvest_timer(mfs_plan p, int prec) {
+    auto &t = p->timer[prec];
+    if (t.used == 0) return MFS_OK;
+    MFS_HIP_TRY(hipEventSynchronize(t.ev[2 * (t.used - 1) + 1]));
+    for (int i = 0; i < t.used; ++i) {
+        float ms = 0.f;
+        MFS_HIP_TRY(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+        t.total_ms += ms;
+        ++t.launches;
+    }
+    t.used = 0;
+    return MFS_OK;
+}
+
 int matvec_impl(mfs_plan p, const double *gamma, double *out, int prec, const int32_t *sys_active, hipStream_t s) {
     MFS_TRY(precond_fwd(p, gamma, prec, true, nullptr, prec, s));
     P2PLaunch L = fwd_launch(p, prec);
@@ -935,6 +1005,17 @@ int matvec_impl(mfs_plan p, const double *gamma, double *out, int prec, const in
     L.addend = gamma;
     L.out = out;
     L.sys_active = sys_active;
+    if (p->timing) {
+        auto &t = p->timer[prec];
+        if (t.ev.empty()) {
+            t.ev.resize(512);
+            for (auto &e : t.ev) MFS_HIP_TRY(hipEventCreate(&e));
+        }
+        if (2 * t.used >= (int)t.ev.size()) MFS_TRY(harvest_timer(p, prec));
+        L.ev_start = t.ev[2 * t.used];
+        L.ev_stop = t.ev[2 * t.used + 1];
+        ++t.used;
+    }
     return launch_p2p(p->p2p_fwd, L, s);
 }
 
@@ -1286,4 +1367,29 @@ extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double 
                                     p->bw_gt.as<double>(), p->bw_gs.as<double>(), grad_centre, s));
     MFS_HIP_TRY(hipStreamSynchronize(s));
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// instrumentation
+// ---------------------------------------------------------------------------
+extern "C" int mfs_plan_set_timing(mfs_plan p, int32_t enable) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    p->timing = enable != 0;
+    return MFS_OK;
+}
+
+extern "C" int mfs_plan_timing(mfs_plan p, int32_t prec, int32_t reset, int64_t *launches, double *total_ms,
+                               double *pairs_per_launch) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    MFS_TRY(check_prec(prec));
+    MFS_TRY(harvest_timer(p, prec));
+    auto &t = p->timer[prec];
+    if (launches) *launches = t.launches;
+    if (total_ms) *total_ms = t.total_ms;
+    if (pairs_per_launch) *pairs_per_launch = p->offbody_pairs;
+    if (reset) {
+        t.launches = 0;
+        t.total_ms = 0.0;
+    }
+    return MFS_OK;
 }

@@ -97,6 +97,8 @@ struct P2PLaunch {
     double *partial = nullptr;            // [n_split][n_val] when n_split > 1
     const double *addend = nullptr;       // added once to the output (may be null)
     int64_t n_val = 0;                    // output length
+    hipEvent_t ev_start = nullptr;        // optional events recorded right around the pair kernel
+    hipEvent_t ev_stop = nullptr;
 };
 
 // Host-side description of a pair-sum launch.
@@ -132,19 +134,29 @@ int launch_p2p_grad(const P2PPlan &pp, const P2PLaunch &L, const double *lane_ve
 // ---------------------------------------------------------------------------
 // Block (one-body) kernels (block_kernels.hip)
 // ---------------------------------------------------------------------------
-struct GemmTile { int32_t group, m0, n0, pad; };
+struct GemmTile { int32_t group, m0, n0, k0, k1, split; };
 struct GemmGroup {
     int32_t M, K;             // A is M x K row-major (lda = K)
     int32_t col_begin, ncol;  // columns [col_begin, col_begin+ncol) of the column table
     int64_t a_off;            // element offset of A in the factor pool
 };
+// One grouped-GEMM launch (device tables built at plan creation).
+struct GemmLaunch {
+    int n_tiles = 0;
+    int n_split = 1;
+    int n_cols = 0;
+    const GemmTile *tiles = nullptr;
+    const GemmGroup *groups = nullptr;
+    const int32_t *col_group = nullptr;  // [n_cols] group of every column
+    int64_t part_col_stride = 0;         // partial buffer: [n_split][n_cols][part_col_stride]
+    int64_t part_split_stride = 0;
+    int vec4 = 0;  // every A row start and B column start is 16-byte aligned (float4 / double2 loads)
+};
 
-int launch_gemm_f32(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const float *Apool,
-                    const float *B, const int64_t *b_col_off, float *C, const int64_t *c_col_off,
-                    hipStream_t s);
-int launch_gemm_f64(int n_tiles, const GemmTile *tiles, const GemmGroup *groups, const double *Apool,
-                    const double *B, const int64_t *b_col_off, double *C, const int64_t *c_col_off,
-                    hipStream_t s);
+int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, const int64_t *b_col_off, float *C,
+                    const int64_t *c_col_off, float *partial, hipStream_t s);
+int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, const int64_t *b_col_off, double *C,
+                    const int64_t *c_col_off, double *partial, hipStream_t s);
 
 // Per-body view used by rotation / projection / extraction kernels.
 struct BodyView {

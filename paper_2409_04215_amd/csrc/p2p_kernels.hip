@@ -370,6 +370,7 @@ int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) {
     a.accumulate = direct ? (L.accumulate ? 1 : 0) : 0;
     a.out_stride = L.n_val;
     const dim3 grid((unsigned)pp.items.size());
+    if (L.ev_start) MFS_HIP_TRY(hipEventRecord(L.ev_start, s));
     if (L.prec == MFS_MIXED) {
         if (pp.tpl == 2)
             p2p_mixed_kernel<2><<<grid, BLOCK, 0, s>>>(a, (const float4 *)L.trg_off, (const SrcS32 *)L.srcS,
@@ -386,6 +387,7 @@ int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) {
                                                      (const SrcL64 *)L.srcL);
     }
     MFS_HIP_TRY(hipGetLastError());
+    if (L.ev_stop) MFS_HIP_TRY(hipEventRecord(L.ev_stop, s));
     if (!direct) {
         const int64_t n = L.n_val;
         reduce_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, L.partial, L.n_val, pp.n_split, L.addend,

@@ -71,6 +71,8 @@ def lib():
         L.mfs_gmres_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, _i32p, _dp, _vp]
         L.mfs_extract.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.mfs_plan_set_timing.argtypes = [_vp, ctypes.c_int32]
+        L.mfs_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i64p, _dp, _dp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
         _lib = L
@@ -283,6 +285,17 @@ class Plan:
         gamma, iters, relres, st = self.gmres_solve(b, tol, max_iter, max_refine, stream=stream)
         out, _ = self.extract(gamma, s0, stream=stream)
         return out, dict(gamma=gamma, s0=s0, b=b, iters=iters, relres=relres, status=st)
+
+    def set_timing(self, enable: bool = True):
+        """Bracket every matvec pair-sum launch with HIP events (see mfs.h)."""
+        _check(lib().mfs_plan_set_timing(self._h, int(enable)), "mfs_plan_set_timing")
+
+    def timing(self, prec: int, reset: bool = False):
+        """(launches, total kernel ms, off-body pairs per launch) of the matvec pair sums."""
+        n, ms, pairs = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().mfs_plan_timing(self._h, int(prec), int(reset), ctypes.byref(n), ctypes.byref(ms),
+                                     ctypes.byref(pairs)), "mfs_plan_timing")
+        return n.value, ms.value, pairs.value
 
     def solve_backward(self, gamma, s0, grad_out, tol=1e-5, max_iter=200, max_refine=3, stream=None):
         n_sys = len(self.sys_kind)
