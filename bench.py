@@ -56,6 +56,25 @@ def _pairs(wl):
     return float(off), float(sum(n_trg) * tot_src)
 
 
+def _counter_traffic(workload: str):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"p2p_mixed_stokes_{workload}_pmc.txt")
+    src = os.path.join(ROOT, "paper_2409_04215_amd", "csrc", "p2p_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("machine-readable: "):
+            rec = json.loads(line[len("machine-readable: "):])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if not rec or rec.get("source_sha256_16") != sha:
+        return None
+    return rec
+
+
 def _timed_solves(plan, net, tol, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -159,9 +178,10 @@ def main():
         n = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads and writes calib_copy_mib MiB
         torch.cuda.synchronize()
 
+    traffic = _counter_traffic(args.workload)
     avg_ms = ms_mx / max(n_mx, 1)
     achieved = FLOPS_PER_PAIR[kind] * ppl / (avg_ms * 1e-3) / 1e12
     avg64_ms = ms64 / max(n64, 1)
@@ -182,7 +202,12 @@ def main():
                    "collocation_per_body": 800, "kernel": "stokes mobility", "gmres_tol": args.tol,
                    "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_pairs},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": round(traffic["traffic_bytes"]) if traffic else None,
+                     "traffic_fetch_bytes": round(traffic["fetch_bytes"]) if traffic else None,
+                     "traffic_write_bytes": round(traffic["write_bytes"]) if traffic else None,
+                     "ceiling_nonpacked_fp32_tflops": 78.6,
+                     "ceiling_issue_bound_tflops": round(78.6 * FLOPS_PER_PAIR[kind] / (2 * 18), 2),
                      "kernel": "p2p_mixed_kernel<1> (Stokes)", "avg_launch_ms": round(avg_ms, 4),
                      "launches": n_mx, "flops_per_pair": FLOPS_PER_PAIR[kind], "pairs_per_launch": ppl},
         "solve_time_mixed_s": round(step_s, 5),
