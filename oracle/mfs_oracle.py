@@ -349,8 +349,12 @@ class Problem:
         return v[self.src_off[k]:self.src_off[k + 1]]
 
     # -- one-body pieces -----------------------------------------------------
-    def _rot_blocks(self, R, n):
-        return np.kron(np.eye(n), R)
+    @staticmethod
+    def _rotate(R, v, transpose=False):
+        """Apply the block-diagonal rotation diag(R, ..., R) (or its transpose)
+        to a point-major stacked vector v = [v_1; v_2; ...]."""
+        pts = v.reshape(-1, 3)
+        return (pts @ R).reshape(-1) if transpose else (pts @ R.T).reshape(-1)
 
     def pinv_apply(self, k: int, gamma_k: np.ndarray) -> np.ndarray:
         """S_L^(k)+ gamma^(k) (eq. (pseudo); Remark "congruent" for rotated copies)."""
@@ -358,8 +362,7 @@ class Problem:
         F = self.factors[b.factor_key]
         if self.per_body or self.kind == LAPLACE:
             return F.apply(gamma_k)
-        M, N = b.X.shape[0], b.Y.shape[0]
-        return self._rot_blocks(b.rot, N) @ F.apply(self._rot_blocks(b.rot, M).T @ gamma_k)
+        return self._rotate(b.rot, F.apply(self._rotate(b.rot, gamma_k, transpose=True)))
 
     def pinv_apply_T(self, k: int, v: np.ndarray) -> np.ndarray:
         """(S_L^(k)+)^T v."""
@@ -367,8 +370,7 @@ class Problem:
         F = self.factors[b.factor_key]
         if self.per_body or self.kind == LAPLACE:
             return F.apply_T(v)
-        M, N = b.X.shape[0], b.Y.shape[0]
-        return self._rot_blocks(b.rot, M) @ F.apply_T(self._rot_blocks(b.rot, N).T @ v)
+        return self._rotate(b.rot, F.apply_T(self._rotate(b.rot, v, transpose=True)))
 
     def project(self, k: int, lam_k: np.ndarray) -> np.ndarray:
         """(I - L^(k)) lambda^(k)."""

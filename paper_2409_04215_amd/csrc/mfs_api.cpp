@@ -524,6 +524,8 @@ int build_gemm_tables(mfs_plan p, hipStream_t s) {
 }
 
 // FP64 SVD of every (shape, kind) S_L on the device; fills the factor pools.
+// Factors of equal size are assembled side by side and factored by one
+// strided-batched SVD (in chunks that keep the scratch under ~4 GB).
 int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t> &shape_src_off,
                   const std::vector<int64_t> &shape_trg_off, hipStream_t s) {
     rocblas_handle h;
@@ -546,57 +548,102 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
     }
     MFS_TRY(p->A64.reserve(std::max<int64_t>(1, pool) * sizeof(double)));
     MFS_TRY(p->A32.reserve(std::max<int64_t>(1, pool) * sizeof(float)));
-    DevBuf SL, Ub, Vb, Sv, E, info, work, pts, gi, ones;
-    for (auto &F : p->factors) {
-        const int N = d->shape_n_src[F.shape], M = d->shape_n_trg[F.shape];
-        const int m = F.dM, n = F.dN;
-        MFS_TRY(SL.reserve((size_t)m * n * sizeof(double)));
-        MFS_TRY(Ub.reserve((size_t)m * n * sizeof(double)));
-        MFS_TRY(Vb.reserve((size_t)n * n * sizeof(double)));
-        MFS_TRY(Sv.reserve((size_t)n * sizeof(double)));
-        MFS_TRY(E.reserve((size_t)n * sizeof(double)));
-        MFS_TRY(info.reserve(sizeof(rocblas_int)));
-        MFS_TRY(work.reserve((size_t)3 * M * 6 * sizeof(double)));
-        std::vector<double> hp(3 * (size_t)(M + N));
-        std::memcpy(hp.data(), d->shape_trg + 3 * shape_trg_off[F.shape], 3 * (size_t)M * sizeof(double));
-        std::memcpy(hp.data() + 3 * (size_t)M, d->shape_src + 3 * shape_src_off[F.shape], 3 * (size_t)N * sizeof(double));
+    // batches of equal (m, n)
+    std::vector<std::vector<int>> batches;
+    {
+        std::vector<std::pair<std::pair<int, int>, int>> keyed;
+        for (int f = 0; f < (int)p->factors.size(); ++f)
+            keyed.push_back({{p->factors[f].dM, p->factors[f].dN}, f});
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        const double cap = 4e9;
+        for (size_t i = 0; i < keyed.size(); ++i) {
+            const int m = keyed[i].first.first, n = keyed[i].first.second;
+            const double bytes = 8.0 * ((double)2 * m * n + (double)n * n);
+            const size_t per = (size_t)std::max(1.0, cap / bytes);
+            if (batches.empty() || p->factors[batches.back()[0]].dM != m || p->factors[batches.back()[0]].dN != n ||
+                batches.back().size() >= per)
+                batches.push_back({});
+            batches.back().push_back(keyed[i].second);
+        }
+    }
+    DevBuf SL, Ub, Vb, Sv, E, info, work, pts, gi, inv;
+    for (auto &bt : batches) {
+        const int B = (int)bt.size();
+        const int m = p->factors[bt[0]].dM, n = p->factors[bt[0]].dN;
+        const int64_t smn = (int64_t)m * n, snn = (int64_t)n * n;
+        MFS_TRY(SL.reserve((size_t)B * smn * sizeof(double)));
+        MFS_TRY(Ub.reserve((size_t)B * smn * sizeof(double)));
+        MFS_TRY(Vb.reserve((size_t)B * snn * sizeof(double)));
+        MFS_TRY(Sv.reserve((size_t)B * n * sizeof(double)));
+        MFS_TRY(E.reserve((size_t)B * n * sizeof(double)));
+        MFS_TRY(info.reserve((size_t)B * sizeof(rocblas_int)));
+        // geometry of every factor of the batch, then assembly of each S_L
+        int maxM = 0;
+        std::vector<double> hp, hg;
+        std::vector<int64_t> pts_off;
+        for (int f : bt) {
+            const Factor &F = p->factors[f];
+            const int N = d->shape_n_src[F.shape], M = d->shape_n_trg[F.shape];
+            maxM = std::max(maxM, M);
+            pts_off.push_back((int64_t)hp.size());
+            hp.insert(hp.end(), d->shape_trg + 3 * shape_trg_off[F.shape],
+                      d->shape_trg + 3 * (shape_trg_off[F.shape] + M));
+            hp.insert(hp.end(), d->shape_src + 3 * shape_src_off[F.shape],
+                      d->shape_src + 3 * (shape_src_off[F.shape] + N));
+            double G[36], Gi[36];
+            gram6(d->shape_src + 3 * shape_src_off[F.shape], N, G);
+            if (F.kind == MFS_STOKES && !inv6(G, Gi)) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
+            if (F.kind != MFS_STOKES) std::fill(Gi, Gi + 36, 0.0);
+            hg.insert(hg.end(), Gi, Gi + 36);
+        }
         MFS_TRY(upload_vec(pts, hp, s));
-        double G[36], Gi[36];
-        gram6(d->shape_src + 3 * shape_src_off[F.shape], N, G);
-        if (F.kind == MFS_STOKES && !inv6(G, Gi)) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
-        std::vector<double> gv(Gi, Gi + 36);
-        MFS_TRY(upload_vec(gi, gv, s));
-        MFS_TRY(launch_assemble_SL(F.kind, M, N, pts.as<double>(), pts.as<double>() + 3 * (size_t)M, gi.as<double>(),
-                                   p->mu, SL.as<double>(), work.as<double>(), s));
-        rocblas_status st = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, m, n,
-                                             SL.as<double>(), m, Sv.as<double>(), Ub.as<double>(), m, Vb.as<double>(),
-                                             n, E.as<double>(), rocblas_outofplace, info.as<rocblas_int>());
-        if (st != rocblas_status_success) return fail(MFS_EHIP, "rocsolver_dgesvd failed");
-        std::vector<double> sv(n);
-        rocblas_int hinfo = 0;
-        MFS_HIP_TRY(hipMemcpyAsync(sv.data(), Sv.ptr, n * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFS_HIP_TRY(hipMemcpyAsync(&hinfo, info.ptr, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+        MFS_TRY(upload_vec(gi, hg, s));
+        MFS_TRY(work.reserve((size_t)3 * maxM * 6 * sizeof(double)));
+        for (int q = 0; q < B; ++q) {
+            const Factor &F = p->factors[bt[q]];
+            const int N = d->shape_n_src[F.shape], M = d->shape_n_trg[F.shape];
+            const double *P = pts.as<double>() + pts_off[q];
+            MFS_TRY(launch_assemble_SL(F.kind, M, N, P, P + 3 * (size_t)M, gi.as<double>() + 36 * q, p->mu,
+                                       SL.as<double>() + q * smn, work.as<double>(), s));
+        }
+        rocblas_status st = rocsolver_dgesvd_strided_batched(
+            h, rocblas_svect_singular, rocblas_svect_singular, m, n, SL.as<double>(), m, smn, Sv.as<double>(), n,
+            Ub.as<double>(), m, smn, Vb.as<double>(), n, snn, E.as<double>(), n, rocblas_outofplace,
+            info.as<rocblas_int>(), B);
+        if (st != rocblas_status_success) return fail(MFS_EHIP, "rocsolver_dgesvd_strided_batched failed");
+        std::vector<double> sv((size_t)B * n);
+        std::vector<rocblas_int> hinfo(B);
+        MFS_HIP_TRY(hipMemcpyAsync(sv.data(), Sv.ptr, sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipMemcpyAsync(hinfo.data(), info.ptr, B * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
         MFS_HIP_TRY(hipStreamSynchronize(s));
-        if (hinfo != 0) return fail(MFS_ENUMERIC, "SVD did not converge");
-        F.ratio = sv[n - 1] / sv[0];
-        p->min_ratio = std::min(p->min_ratio, F.ratio);
-        if (!(F.ratio > 1e-14))
-            return fail(MFS_ENUMERIC, "sigma_min/sigma_max = " + std::to_string(F.ratio) + " <= 1e-14");
-        std::vector<double> inv(n);
-        for (int i = 0; i < n; ++i) inv[i] = 1.0 / sv[i];
-        MFS_TRY(upload_vec(ones, inv, s));
+        std::vector<double> hinv((size_t)B * n);
+        for (int q = 0; q < B; ++q) {
+            Factor &F = p->factors[bt[q]];
+            if (hinfo[q] != 0) return fail(MFS_ENUMERIC, "SVD did not converge");
+            const double *svq = sv.data() + (size_t)q * n;
+            F.ratio = svq[n - 1] / svq[0];
+            p->min_ratio = std::min(p->min_ratio, F.ratio);
+            if (!(F.ratio > 1e-14))
+                return fail(MFS_ENUMERIC, "sigma_min/sigma_max = " + std::to_string(F.ratio) + " <= 1e-14");
+            for (int i = 0; i < n; ++i) hinv[(size_t)q * n + i] = 1.0 / svq[i];
+        }
+        MFS_TRY(upload_vec(inv, hinv, s));
         double *A64 = p->A64.as<double>();
         float *A32 = p->A32.as<float>();
-        // U^T (n x m): row r = column r of U (column-major, ld m)
-        MFS_TRY(launch_make_factor(n, m, Ub.as<double>(), m, false, nullptr, nullptr, A64 + F.ut_off, A32 + F.ut_off, s));
-        // U (m x n) row-major: U[r][c] = Ucm[c*m + r]
-        MFS_TRY(launch_make_factor(m, n, Ub.as<double>(), m, true, nullptr, nullptr, A64 + F.u_off, A32 + F.u_off, s));
-        // W = V Sigma^{-1}: the V^T output (column-major, ld n) read row-major is V
-        MFS_TRY(launch_make_factor(n, n, Vb.as<double>(), n, false, nullptr, ones.as<double>(), A64 + F.w_off,
-                                   A32 + F.w_off, s));
-        // W^T = Sigma^{-1} V^T
-        MFS_TRY(launch_make_factor(n, n, Vb.as<double>(), n, true, ones.as<double>(), nullptr, A64 + F.wt_off,
-                                   A32 + F.wt_off, s));
+        for (int q = 0; q < B; ++q) {
+            const Factor &F = p->factors[bt[q]];
+            const double *U = Ub.as<double>() + q * smn, *V = Vb.as<double>() + q * snn;
+            const double *iv = inv.as<double>() + (size_t)q * n;
+            // U^T (n x m): row r = column r of U (column-major, ld m)
+            MFS_TRY(launch_make_factor(n, m, U, m, false, nullptr, nullptr, A64 + F.ut_off, A32 + F.ut_off, s));
+            // U (m x n) row-major: U[r][c] = Ucm[c*m + r]
+            MFS_TRY(launch_make_factor(m, n, U, m, true, nullptr, nullptr, A64 + F.u_off, A32 + F.u_off, s));
+            // W = V Sigma^{-1}: the V^T output (column-major, ld n) read row-major is V
+            MFS_TRY(launch_make_factor(n, n, V, n, false, nullptr, iv, A64 + F.w_off, A32 + F.w_off, s));
+            // W^T = Sigma^{-1} V^T
+            MFS_TRY(launch_make_factor(n, n, V, n, true, iv, nullptr, A64 + F.wt_off, A32 + F.wt_off, s));
+        }
         MFS_HIP_TRY(hipStreamSynchronize(s));
     }
     return MFS_OK;

@@ -1,0 +1,111 @@
+"""Gradients of a mobility loss with respect to the particle centres: the
+adjoint solve (mfs_solve_backward, the backward pair kernels, the adjoint
+matvec) against the oracle's adjoint gradient and against central finite
+differences of forward solves.
+
+Loss J = sum_k |U^(k)|^2 (velocities and angular velocities), so
+dJ/dU = 2 U.  Tolerances (rel_inf over the (P, 3) gradient):
+* FP64 plan, tol 1e-12 on both solves: 1e-8 against the oracle.
+* MIXED plan, tol 1e-8 (FP64 true-residual refinement on both solves): 1e-5.
+* Finite differences (h = 1e-5, FP64 solves at tol 1e-12) of the directional
+  derivative along a unit direction v: |fd - g.v| <= 1e-6 |g|_2 for the FP64
+  gradient and 1e-5 |g|_2 for the mixed one (the error of a directional
+  derivative is measured against the gradient's norm, not against g.v, which
+  can be small; truncation ~h^2, solver noise ~1e-12 J / h).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import net_flat, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+def _gpu_grad(wl, prec, tol):
+    mfs = _mfs()
+    plan = mfs.Plan.from_workload(wl, prec)
+    out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
+    g, iters, relres, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+    assert st == mfs.MFS_OK
+    U = out.cpu().numpy().reshape(-1, 6)
+    return float(np.sum(U * U)), g.cpu().numpy(), iters
+
+
+def test_gradient_matches_oracle_small():
+    mfs = _mfs()
+    wl = W.small_cluster(3, W.STOKES, 60, 130, seed=31, axes=(1.0, 1.0, 1.0))
+    J_ref, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    J64, g64, _ = _gpu_grad(wl, mfs.FP64, 1e-12)
+    Jmx, gmx, _ = _gpu_grad(wl, mfs.MIXED, 1e-8)
+    print("J", J_ref, J64, Jmx, "grad err fp64", rel_inf(g64, g_ref), "mixed", rel_inf(gmx, g_ref))
+    assert abs(J64 - J_ref) <= 1e-10 * J_ref
+    assert rel_inf(g64, g_ref) <= 1e-8
+    assert rel_inf(gmx, g_ref) <= 1e-5
+
+
+def test_gradient_ellipsoids_matches_oracle():
+    mfs = _mfs()
+    wl = W.small_cluster(4, W.STOKES, 45, 301, seed=32)
+    _, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    _, g64, _ = _gpu_grad(wl, mfs.FP64, 1e-12)
+    _, gmx, _ = _gpu_grad(wl, mfs.MIXED, 1e-8)
+    assert rel_inf(g64, g_ref) <= 1e-8
+    assert rel_inf(gmx, g_ref) <= 1e-5
+
+
+def test_autograd_function():
+    mfs = _mfs()
+    wl = W.small_cluster(3, W.STOKES, 60, 130, seed=33, axes=(1.0, 1.0, 1.0))
+    _, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    spec = dict(precision=mfs.MIXED, sys_body_ptr=wl.sys_body_ptr, sys_kind=wl.sys_kind, rot=wl.rot,
+                shape_of_body=wl.shape_of_body, shape_src=[s.src for s in wl.shapes],
+                shape_trg=[s.trg for s in wl.shapes], mu=1.0, net=_dev(net_flat(wl)), tol=1e-8)
+    centre = torch.tensor(wl.centre, dtype=torch.float64, device="cuda", requires_grad=True)
+    U = mfs.MobilitySolve.apply(centre, spec)
+    loss = (U * U).sum()
+    loss.backward()
+    assert rel_inf(centre.grad.cpu().numpy(), g_ref) <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_gradient_directional_fd_spheres_200():
+    """Full-size workload (200 unit spheres, N=400, M=800): mixed adjoint
+    gradient vs central differences of FP64 GPU solves along random directions."""
+    mfs = _mfs()
+    wl = W.spheres_200()
+    J, g, iters = _gpu_grad(wl, mfs.MIXED, 1e-8)
+    _, g64, _ = _gpu_grad(wl, mfs.FP64, 1e-10)
+    print("J", J, "adjoint iters", iters, "mixed vs fp64 grad", rel_inf(g, g64))
+    assert rel_inf(g, g64) <= 1e-5
+    rng = np.random.default_rng(7)
+    h = 1e-5
+    base = wl.centre.copy()
+    for _ in range(2):
+        v = rng.standard_normal(base.shape)
+        v /= np.linalg.norm(v)
+        Js = []
+        for sgn in (1.0, -1.0):
+            wl.centre = base + sgn * h * v
+            plan = mfs.Plan.from_workload(wl, mfs.FP64)
+            out, _ = plan.solve(_dev(net_flat(wl)), tol=1e-12)
+            Js.append(float((out * out).sum()))
+            plan.close()
+        wl.centre = base
+        fd = (Js[0] - Js[1]) / (2 * h)
+        ad = float(np.sum(g * v))
+        ad64 = float(np.sum(g64 * v))
+        print("directional fd", fd, "mixed", ad, "fp64", ad64)
+        assert abs(fd - ad64) <= 1e-6 * np.linalg.norm(g64)
+        assert abs(fd - ad) <= 1e-5 * np.linalg.norm(g)
