@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default pair-sum launch shape")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration runs)")
     args = ap.parse_args()
@@ -152,6 +153,10 @@ def main():
     setup_s = time.perf_counter() - t0
     plan_64 = mfs.Plan.from_workload(wl, mfs.FP64)
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = plan_mx.autotune(mfs.MIXED, reps=3)
+        plan_64.autotune(mfs.FP64, reps=2)
     for _ in range(args.warmup):
         plan_mx.solve(net, tol=args.tol)
     plan_mx.set_timing(True)
@@ -222,6 +227,7 @@ def main():
         "p2p_kernel_ginter_s_fp64": round(ppl / (avg64_ms * 1e-3) / 1e9, 2) if n64 else None,
         "rel_diff_U_mixed_vs_fp64_gpu": diff,
         "setup_s": round(setup_s, 3),
+        "autotuned_launch": {"targets_per_lane": tuned[0], "work_items": tuned[1]} if tuned else None,
     }
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)

@@ -232,6 +232,19 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
  * kernel time in ms (synchronises on the last recorded event) and the number
  * of off-body pairs one launch evaluates; reset != 0 clears the counters. */
 int mfs_plan_set_timing(mfs_plan plan, int32_t enable);
+
+/* Options.  mfs_plan_set_graph: with enable != 0, mfs_gmres_solve replays the
+ * Krylov matvec from a hipGraph, captured on first use per (precision,
+ * direction) on a library-owned stream with fixed buffers (the Krylov column
+ * is copied into a fixed input first); the captured work holds kernel
+ * launches only.  Ignored while timing is enabled.  mfs_plan_autotune: times
+ * the matvec pair sum for candidate launch shapes (1 or 2 targets per lane x
+ * 1024..16384 work items, which sets the source split) on `stream`, reps
+ * launches each, keeps the fastest for the forward and transposed sums, and
+ * reports it ([host] outputs, may be NULL).  Synchronous. */
+int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
+int mfs_plan_autotune(mfs_plan plan, int32_t prec, int32_t reps, int32_t *best_tpl, int32_t *best_min_items,
+                      double *best_ms, void *stream);
 int mfs_plan_timing(mfs_plan plan, int32_t prec, int32_t reset, int64_t *launches, double *total_ms,
                     double *pairs_per_launch);
 

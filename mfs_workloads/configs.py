@@ -239,3 +239,21 @@ def small_cluster(n_body: int, kind: int, n_src: int, n_trg: int, seed: int, axe
 def random_vector(n: int, seed: int) -> np.ndarray:
     """A seeded N(0,1) vector (matvec inputs for parity tests)."""
     return np.random.default_rng(np.random.SeedSequence(9000 + seed)).standard_normal(n)
+
+
+def smooth_vector(wl: Workload, seed: int) -> np.ndarray:
+    """A seeded smooth field on the collocation points (gamma layout): per body,
+    a random polynomial of degree 2 in the body-frame coordinates (a vector
+    polynomial for Stokes systems, scalar for Laplace).  Stands in for the
+    smooth surface data GMRES works with."""
+    rng = np.random.default_rng(np.random.SeedSequence(9500 + seed))
+    parts = []
+    for s in range(wl.n_sys):
+        dim = 3 if wl.sys_kind[s] == STOKES else 1
+        for b in range(int(wl.sys_body_ptr[s]), int(wl.sys_body_ptr[s + 1])):
+            x = wl.shapes[wl.shape_of_body[b]].trg
+            feats = np.concatenate([np.ones((x.shape[0], 1)), x, x * x, x[:, [0]] * x[:, [1]],
+                                    x[:, [1]] * x[:, [2]], x[:, [0]] * x[:, [2]]], axis=1)
+            coef = rng.standard_normal((feats.shape[1], dim))
+            parts.append((feats @ coef).reshape(-1))
+    return np.concatenate(parts)

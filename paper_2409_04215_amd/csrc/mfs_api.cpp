@@ -355,10 +355,21 @@ struct mfs_plan_s {
     } timer[2];
     bool timing = false;
     double offbody_pairs = 0.0;
+    // hipGraph replay of the GMRES matvec: captured once per (precision, direction)
+    bool use_graph = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    DevBuf stage;  // fixed input buffer of the captured matvec
+    // autotuned pair-sum launch shape
+    int tuned_tpl = 1, tuned_min_items = 2048;
 
     ~mfs_plan_s() {
         for (auto &t : timer)
             for (auto e : t.ev) (void)hipEventDestroy(e);
+        for (auto &row : graph)
+            for (auto &g : row)
+                if (g) (void)hipGraphExecDestroy(g);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
     }
     std::vector<VecChunk> h_chunks;
     std::vector<int32_t> h_sys_chunk_ptr;
@@ -1173,6 +1184,42 @@ int sys_norms(mfs_plan p, const double *x, std::vector<double> &out, hipStream_t
 
 typedef int (*MatvecFn)(mfs_plan, const double *, double *, int, const int32_t *, hipStream_t);
 
+// w = A v for the GMRES loop (w must be the plan's Krylov work vector).  With
+// graphs enabled the matvec is captured once per (precision, direction) on a
+// library stream with fixed buffers (v is staged into p->stage first) and
+// replayed on the caller's stream; the captured work holds kernel launches
+// only (no memset, no host synchronisation).
+int apply_A(mfs_plan p, MatvecFn A, const double *v, double *w, int prec, hipStream_t s) {
+    if (!p->use_graph || p->timing) return A(p, v, w, prec, p->sys_active.as<int32_t>(), s);
+    const int dir = A == matvec_impl ? 0 : 1;
+    MFS_TRY(p->stage.reserve(std::max<int64_t>(1, p->n_gamma) * sizeof(double)));
+    hipGraphExec_t &ex = p->graph[prec][dir];
+    if (!ex) {
+        if (!p->capture_stream) MFS_HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+        hipGraph_t g = nullptr;
+        MFS_HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+        const int st = A(p, p->stage.as<double>(), p->Wv.as<double>(), prec, p->sys_active.as<int32_t>(),
+                         p->capture_stream);
+        hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+        if (st < 0) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(MFS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ex = nullptr;
+            return fail(MFS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    if (w != p->Wv.as<double>()) return fail(MFS_EINVAL, "internal: graph output must be the Krylov work vector");
+    MFS_HIP_TRY(hipMemcpyAsync(p->stage.ptr, v, p->n_gamma * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MFS_HIP_TRY(hipGraphLaunch(ex, s));
+    return MFS_OK;
+}
+
 // One unrestarted GMRES attempt on A dx = r for every active system; x += dx.
 // target[s]: absolute residual target.  counts[s] += matvecs spent.  est[s]: final estimate.
 int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, const std::vector<double> &target,
@@ -1216,7 +1263,7 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         }
         if (!any) break;
         MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MFS_TRY(A(p, V + (int64_t)j * n, w, prec, p->sys_active.as<int32_t>(), s));
+        MFS_TRY(apply_A(p, A, V + (int64_t)j * n, w, prec, s));
         for (int sy = 0; sy < S; ++sy) counts[sy] += live[sy];
         // classical Gram-Schmidt, twice
         double *dots = p->dots.as<double>();
@@ -1438,5 +1485,96 @@ extern "C" int mfs_plan_timing(mfs_plan p, int32_t prec, int32_t reset, int64_t 
         t.launches = 0;
         t.total_ms = 0.0;
     }
+    return MFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// options: graphs and autotuning
+// ---------------------------------------------------------------------------
+extern "C" int mfs_plan_set_graph(mfs_plan p, int32_t enable) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    p->use_graph = enable != 0;
+    return MFS_OK;
+}
+
+// Times candidate launch shapes of the matvec pair sum (targets per lane x
+// number of work items, which sets the source split) with HIP events on
+// `stream` and keeps the fastest for the forward and transposed sums.
+// Grows the pair-sum partial workspace to at least n doubles, keeping every other
+// buffer (the caller has synchronised; graphs are re-captured afterwards).
+int grow_partial(mfs_plan p, int64_t n) {
+    if ((size_t)n * sizeof(double) <= p->partial.bytes) return MFS_OK;
+    return p->partial.reserve((size_t)n * sizeof(double));
+}
+
+extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t *best_tpl,
+                                 int32_t *best_min_items, double *best_ms, void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    MFS_TRY(check_prec(prec));
+    if (reps < 1 || reps > 100) return fail(MFS_EINVAL, "reps must be in [1, 100]");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> src_row(p->src_row), trg_row(p->trg_row);
+    hipEvent_t e0, e1;
+    MFS_HIP_TRY(hipEventCreate(&e0));
+    MFS_HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    int btpl = p->tuned_tpl, bmi = p->tuned_min_items;
+    const int tpls[2] = {1, 2};
+    const int mis[5] = {1024, 2048, 4096, 8192, 16384};
+    int status = MFS_OK;
+    for (int tpl : tpls) {
+        for (int mi : mis) {
+            P2PPlan cand;
+            status = build_p2p_items(cand, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                                     p->gam_off.data(), p->kind.data(), p->mu, tpl, mi, s);
+            if (status < 0) break;
+            const int64_t need = (cand.n_split > 1 ? cand.n_split : 1) * std::max<int64_t>(1, p->n_gamma);
+            if ((size_t)need * sizeof(double) > p->partial.bytes) {
+                MFS_HIP_TRY(hipStreamSynchronize(s));
+                status = grow_partial(p, need);
+                if (status < 0) break;
+            }
+            P2PLaunch L = fwd_launch(p, prec);
+            L.skip_same = true;
+            L.out = p->ws_g64.as<double>();
+            status = launch_p2p(cand, L, s);  // warm-up
+            if (status < 0) break;
+            MFS_HIP_TRY(hipEventRecord(e0, s));
+            for (int r = 0; r < reps && status >= 0; ++r) status = launch_p2p(cand, L, s);
+            MFS_HIP_TRY(hipEventRecord(e1, s));
+            MFS_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            MFS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < best) {
+                best = ms / reps;
+                btpl = tpl;
+                bmi = mi;
+            }
+        }
+        if (status < 0) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status < 0) return status;
+    p->tuned_tpl = btpl;
+    p->tuned_min_items = bmi;
+    MFS_TRY(build_p2p_items(p->p2p_fwd, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                            p->gam_off.data(), p->kind.data(), p->mu, btpl, bmi, s));
+    MFS_TRY(build_p2p_items(p->p2p_tr, p->n_sys, p->sys_body_ptr.data(), src_row.data(), trg_row.data(),
+                            p->lam_off.data(), p->kind.data(), p->mu, btpl, bmi, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_fwd.n_split, 1) * std::max<int64_t>(1, p->n_gamma)));
+    MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_tr.n_split, 1) * std::max<int64_t>(1, p->n_lambda)));
+    // captured graphs hold the old work tables and buffers
+    for (auto &row : p->graph)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    if (best_tpl) *best_tpl = btpl;
+    if (best_min_items) *best_min_items = bmi;
+    if (best_ms) *best_ms = best;
     return MFS_OK;
 }

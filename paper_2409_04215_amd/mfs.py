@@ -73,6 +73,8 @@ def lib():
         L.mfs_extract.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.mfs_plan_set_timing.argtypes = [_vp, ctypes.c_int32]
         L.mfs_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i64p, _dp, _dp]
+        L.mfs_plan_set_graph.argtypes = [_vp, ctypes.c_int32]
+        L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
         _lib = L
@@ -296,6 +298,18 @@ class Plan:
         _check(lib().mfs_plan_timing(self._h, int(prec), int(reset), ctypes.byref(n), ctypes.byref(ms),
                                      ctypes.byref(pairs)), "mfs_plan_timing")
         return n.value, ms.value, pairs.value
+
+    def set_graph(self, enable: bool = True):
+        """Replay the GMRES matvec from a captured hipGraph (see mfs.h)."""
+        _check(lib().mfs_plan_set_graph(self._h, int(enable)), "mfs_plan_set_graph")
+
+    def autotune(self, prec: Optional[int] = None, reps: int = 3, stream=None):
+        """Pick the fastest pair-sum launch shape; returns (targets per lane, work items, ms)."""
+        tpl, mi, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().mfs_plan_autotune(self._h, self.precision if prec is None else int(prec), int(reps),
+                                       ctypes.byref(tpl), ctypes.byref(mi), ctypes.byref(ms), _stream(stream)),
+               "mfs_plan_autotune")
+        return tpl.value, mi.value, ms.value
 
     def solve_backward(self, gamma, s0, grad_out, tol=1e-5, max_iter=200, max_refine=3, stream=None):
         n_sys = len(self.sys_kind)
