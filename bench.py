@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_PAIR = {1: 28.0, 0: 11.0}      # Stokes, Laplace (FMA = 2, rsqrt = 1)
 PEAK_FP32_TFLOPS = 157.3                  # MI355X FP32 vector peak (published)
-WORKLOADS = ("ellipsoids_100", "ellipsoids_1000")
+WORKLOADS = ("ellipsoids_100", "ellipsoids_1000", "batched_64", "spheres_200_grad")
 
 
 def _workload(name: str, kind: int):
@@ -45,15 +45,24 @@ def _workload(name: str, kind: int):
         return W.ellipsoids_100(kind)
     if name == "ellipsoids_1000":
         return W.ellipsoids_1000(kind)
+    if name == "batched_64":
+        return W.batched_64()
+    if name == "spheres_200_grad":
+        return W.spheres_200()
     raise SystemExit(f"unknown workload {name}; choose from {WORKLOADS}")
 
 
-def _pairs(wl):
-    n_src = [wl.shapes[s].src.shape[0] for s in wl.shape_of_body]
-    n_trg = [wl.shapes[s].trg.shape[0] for s in wl.shape_of_body]
-    tot_src = sum(n_src)
-    off = sum(t * (tot_src - s) for t, s in zip(n_trg, n_src))
-    return float(off), float(sum(n_trg) * tot_src)
+def _pairs_per_system(wl):
+    """Per system: (kind, off-body pairs of one matvec, all pairs of the right-hand side)."""
+    out = []
+    for s in range(wl.n_sys):
+        b0, b1 = int(wl.sys_body_ptr[s]), int(wl.sys_body_ptr[s + 1])
+        n_src = [wl.shapes[wl.shape_of_body[b]].src.shape[0] for b in range(b0, b1)]
+        n_trg = [wl.shapes[wl.shape_of_body[b]].trg.shape[0] for b in range(b0, b1)]
+        tot = sum(n_src)
+        out.append((int(wl.sys_kind[s]), float(sum(t * (tot - q) for t, q in zip(n_trg, n_src))),
+                    float(sum(n_trg) * tot)))
+    return out
 
 
 def _counter_traffic(workload: str):
@@ -124,6 +133,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ellipsoids_100", choices=WORKLOADS)
+    ap.add_argument("--kind", default="stokes", choices=("stokes", "laplace"),
+                    help="PDE of the ellipsoid workloads (batched_64 mixes both; spheres_200_grad is Stokes)")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -142,9 +153,10 @@ def main():
     from paper_2409_04215_amd import mfs
 
     torch.cuda.set_device(0)
-    kind = 1  # Stokes mobility
+    kind = 0 if args.kind == "laplace" else 1
+    grad = args.workload == "spheres_200_grad"
     wl = _workload(args.workload, kind)
-    off_pairs, all_pairs = _pairs(wl)
+    per_sys = _pairs_per_system(wl)
     net = torch.tensor(np.concatenate([n.reshape(-1) for n in wl.net]), dtype=torch.float64, device="cuda")
 
     t0 = time.perf_counter()
@@ -157,24 +169,50 @@ def main():
     if not args.no_autotune:
         tuned = plan_mx.autotune(mfs.MIXED, reps=3)
         plan_64.autotune(mfs.FP64, reps=2)
+
+    def step(plan):
+        out, info = plan.solve(net, tol=args.tol)
+        mx, f64 = plan.last_solve()
+        pairs = sum((m + f) * off + rhs for (k, off, rhs), m, f in zip(per_sys, mx, f64))
+        flops_mx = sum(m * off * FLOPS_PER_PAIR[k] for (k, off, rhs), m in zip(per_sys, mx))
+        pairs_mx = sum(m * off for (k, off, rhs), m in zip(per_sys, mx))
+        its = info["iters"]
+        if grad:
+            g, _, _, _ = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=args.tol)
+            amx, af64 = plan.last_solve()
+            # adjoint matvecs (transposed pair sums) + the two position-gradient passes
+            pairs += sum((m + f + 2) * off for (k, off, rhs), m, f in zip(per_sys, amx, af64))
+            its = np.concatenate([its, amx + af64])
+        return out, info, pairs, flops_mx, pairs_mx, its
+
     for _ in range(args.warmup):
-        plan_mx.solve(net, tol=args.tol)
+        step(plan_mx)
     plan_mx.set_timing(True)
     plan_mx.timing(mfs.MIXED, reset=True)
     plan_mx.timing(mfs.FP64, reset=True)
-    step_s, its, res, out_mx = _timed_solves(plan_mx, net, args.tol, args.steps, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_pairs = tot_flops = tot_pairs_mx = 0.0
+    for _ in range(args.steps):
+        out_mx, info_mx, pairs, flops, pairs_mx, its = step(plan_mx)
+        tot_pairs += pairs
+        tot_flops += flops
+        tot_pairs_mx += pairs_mx
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
     n_mx, ms_mx, ppl = plan_mx.timing(mfs.MIXED)
-    n_chk, ms_chk, _ = plan_mx.timing(mfs.FP64)
+    n_chk, _, _ = plan_mx.timing(mfs.FP64)
     plan_mx.set_timing(False)
-    # pairs evaluated per step: every matvec (mixed and the FP64 residual checks) + the right-hand side
-    matvecs_per_step = (n_mx + n_chk) / args.steps
-    pairs_step = matvecs_per_step * off_pairs + all_pairs
-    value = pairs_step / step_s / 1e9
+    value = tot_pairs / args.steps / step_s / 1e9
 
-    # FP64 reference solves on the GPU
     plan_64.solve(net, tol=args.tol)
     plan_64.set_timing(True)
-    fp64_s, its64, res64, out_64 = _timed_solves(plan_64, net, args.tol, args.fp64_steps, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        out_64, info_64, _, _, _, _ = step(plan_64)
+    torch.cuda.synchronize()
+    fp64_s = (time.perf_counter() - t0) / args.fp64_steps
     n64, ms64, _ = plan_64.timing(mfs.FP64)
     plan_64.set_timing(False)
     diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
@@ -186,10 +224,13 @@ def main():
         torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads and writes calib_copy_mib MiB
         torch.cuda.synchronize()
 
-    traffic = _counter_traffic(args.workload)
+    traffic = _counter_traffic(args.workload) if args.workload == "ellipsoids_100" and kind == 1 else None
     avg_ms = ms_mx / max(n_mx, 1)
-    achieved = FLOPS_PER_PAIR[kind] * ppl / (avg_ms * 1e-3) / 1e12
-    avg64_ms = ms64 / max(n64, 1)
+    achieved = tot_flops / (ms_mx * 1e-3) / 1e12 if ms_mx > 0 else 0.0
+    flops_per_pair = tot_flops / max(tot_pairs_mx, 1.0)
+    kinds = sorted(set(k for k, _, _ in per_sys))
+    kind_name = {0: "laplace elastance", 1: "stokes mobility"}
+    off_total = sum(off for _, off, _ in per_sys)
     rec = {
         "metric": "P2P Ginteractions/s + GMRES-to-1e-5 solve time, mixed vs FP64, 1 GPU",
         "value": round(value, 3),
@@ -202,35 +243,36 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 pairs / f64 accumulation, projection and GMRES",
-        "data": "synthetic (seeded random ellipsoid suspension; the paper publishes no cluster files)",
-        "config": {"workload": args.workload, "bodies": wl.n_body, "proxies_per_body": 400,
-                   "collocation_per_body": 800, "kernel": "stokes mobility", "gmres_tol": args.tol,
-                   "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_pairs},
+        "data": "synthetic (seeded random suspensions; the paper publishes no cluster files)",
+        "config": {"workload": args.workload, "systems": wl.n_sys, "bodies": wl.n_body,
+                   "proxies_per_body": int(wl.shapes[0].src.shape[0]),
+                   "collocation_per_body": int(wl.shapes[0].trg.shape[0]),
+                   "kernel": " + ".join(kind_name[k] for k in kinds) + (" + centre gradient" if grad else ""),
+                   "gmres_tol": args.tol, "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": round(traffic["traffic_bytes"]) if traffic else None,
                      "traffic_fetch_bytes": round(traffic["fetch_bytes"]) if traffic else None,
                      "traffic_write_bytes": round(traffic["write_bytes"]) if traffic else None,
-                     "ceiling_nonpacked_fp32_tflops": 78.6,
-                     "ceiling_issue_bound_tflops": round(78.6 * FLOPS_PER_PAIR[kind] / (2 * 18), 2),
-                     "kernel": "p2p_mixed_kernel<1> (Stokes)", "avg_launch_ms": round(avg_ms, 4),
-                     "launches": n_mx, "flops_per_pair": FLOPS_PER_PAIR[kind], "pairs_per_launch": ppl},
+                     "kernel": "p2p_mixed_kernel (matvec pair sum)", "avg_launch_ms": round(avg_ms, 4),
+                     "launches": n_mx, "flops_per_pair": round(flops_per_pair, 3),
+                     "flops_per_launch": tot_flops / max(n_mx, 1)},
         "solve_time_mixed_s": round(step_s, 5),
         "solve_time_fp64_s": round(fp64_s, 5),
         "speedup_mixed_vs_fp64": round(fp64_s / step_s, 3),
-        "matvecs_per_solve_mixed": matvecs_per_step,
-        "fp64_check_matvecs_per_solve": n_chk / args.steps,
-        "matvecs_per_solve_fp64": n64 / max(args.fp64_steps, 1),
-        "relres_mixed_true_fp64": res[-1],
-        "relres_fp64": res64[-1],
-        "p2p_kernel_ginter_s_mixed": round(ppl / (avg_ms * 1e-3) / 1e9, 2),
-        "p2p_kernel_ginter_s_fp64": round(ppl / (avg64_ms * 1e-3) / 1e9, 2) if n64 else None,
-        "rel_diff_U_mixed_vs_fp64_gpu": diff,
+        "matvecs_per_step_mixed": (n_mx + n_chk) / args.steps,
+        "fp64_check_matvecs_per_step": n_chk / args.steps,
+        "iters_per_system_last_step": [int(x) for x in np.asarray(its).reshape(-1)][:128],
+        "relres_mixed_true_fp64_max": float(np.max(info_mx["relres"])),
+        "relres_fp64_max": float(np.max(info_64["relres"])),
+        "p2p_kernel_ginter_s_mixed": round(ppl * n_mx / (ms_mx * 1e-3) / 1e9, 2) if ms_mx > 0 and wl.n_sys == 1 else None,
+        "p2p_kernel_ginter_s_fp64": round(ppl * n64 / (ms64 * 1e-3) / 1e9, 2) if ms64 > 0 and wl.n_sys == 1 else None,
+        "rel_diff_out_mixed_vs_fp64_gpu": diff,
         "setup_s": round(setup_s, 3),
         "autotuned_launch": {"targets_per_lane": tuned[0], "work_items": tuned[1]} if tuned else None,
     }
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl)
+        rec["cpu_baseline"] = cpu_baseline(wl.system(0) if wl.n_sys > 1 else wl)
     print(json.dumps(rec), flush=True)
     return 0
 

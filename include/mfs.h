@@ -232,6 +232,9 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
  * kernel time in ms (synchronises on the last recorded event) and the number
  * of off-body pairs one launch evaluates; reset != 0 clears the counters. */
 int mfs_plan_set_timing(mfs_plan plan, int32_t enable);
+/* Matvecs per system spent by the last mfs_gmres_solve on this plan, split by
+ * precision (the Krylov matvecs and the FP64 true-residual checks) [host][n_sys]. */
+int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_matvecs);
 
 /* Options.  mfs_plan_set_graph: with enable != 0, mfs_gmres_solve replays the
  * Krylov matvec from a hipGraph, captured on first use per (precision,

@@ -362,6 +362,8 @@ struct mfs_plan_s {
     DevBuf stage;  // fixed input buffer of the captured matvec
     // autotuned pair-sum launch shape
     int tuned_tpl = 1, tuned_min_items = 2048;
+    // matvecs per system of the last GMRES solve, by precision
+    std::vector<int32_t> last_mixed, last_fp64;
 
     ~mfs_plan_s() {
         for (auto &t : timer)
@@ -1345,7 +1347,7 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     for (int sy = 0; sy < S; ++sy)
         if (!std::isfinite(bn[sy])) return fail(MFS_ENUMERIC, "non-finite right-hand side");
     std::vector<double> target(S), est(S), rn(S);
-    std::vector<int> counts(S, 0), active(S, 1);
+    std::vector<int> counts(S, 0), active(S, 1), checks(S, 0);
     MFS_TRY(launch_fill(n, 0.0, x, s));
     double *r = p->R.as<double>();
     MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1366,7 +1368,10 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
             std::vector<int32_t> act32(active.begin(), active.end());
             MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
             MFS_TRY(A(p, x, p->Wv.as<double>(), MFS_FP64, p->sys_active.as<int32_t>(), s));
-            for (int sy = 0; sy < S; ++sy) counts[sy] += active[sy];
+            for (int sy = 0; sy < S; ++sy) {
+                counts[sy] += active[sy];
+                checks[sy] += active[sy];
+            }
             MFS_TRY(launch_sub(n, b, p->Wv.as<double>(), r, s));
             std::vector<double> tn;
             MFS_TRY(sys_norms(p, r, tn, s));
@@ -1386,9 +1391,13 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
         for (int sy = 0; sy < S; ++sy)
             if (!(rn[sy] <= tol * bn[sy])) status = MFS_NOT_CONVERGED;
     }
+    p->last_mixed.assign(S, 0);
+    p->last_fp64.assign(S, 0);
     for (int sy = 0; sy < S; ++sy) {
         if (iters) iters[sy] = counts[sy];
         if (relres) relres[sy] = bn[sy] > 0 ? rn[sy] / bn[sy] : 0.0;
+        (p->prec == MFS_MIXED ? p->last_mixed : p->last_fp64)[sy] = counts[sy] - checks[sy];
+        if (p->prec == MFS_MIXED) p->last_fp64[sy] = checks[sy];
     }
     if (status == MFS_NOT_CONVERGED) set_error("GMRES: some system did not reach the tolerance");
     return status;
@@ -1576,5 +1585,15 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
     if (best_tpl) *best_tpl = btpl;
     if (best_min_items) *best_min_items = bmi;
     if (best_ms) *best_ms = best;
+    return MFS_OK;
+}
+
+extern "C" int mfs_plan_last_solve(mfs_plan p, int32_t *mixed_matvecs, int32_t *fp64_matvecs) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    for (int64_t sy = 0; sy < p->n_sys; ++sy) {
+        const bool have = (size_t)sy < p->last_mixed.size();
+        if (mixed_matvecs) mixed_matvecs[sy] = have ? p->last_mixed[sy] : 0;
+        if (fp64_matvecs) fp64_matvecs[sy] = have ? p->last_fp64[sy] : 0;
+    }
     return MFS_OK;
 }

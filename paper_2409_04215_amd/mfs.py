@@ -74,6 +74,7 @@ def lib():
         L.mfs_plan_set_timing.argtypes = [_vp, ctypes.c_int32]
         L.mfs_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i64p, _dp, _dp]
         L.mfs_plan_set_graph.argtypes = [_vp, ctypes.c_int32]
+        L.mfs_plan_last_solve.argtypes = [_vp, _i32p, _i32p]
         L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
@@ -298,6 +299,14 @@ class Plan:
         _check(lib().mfs_plan_timing(self._h, int(prec), int(reset), ctypes.byref(n), ctypes.byref(ms),
                                      ctypes.byref(pairs)), "mfs_plan_timing")
         return n.value, ms.value, pairs.value
+
+    def last_solve(self):
+        """(mixed matvecs, FP64 matvecs) per system of the last GMRES solve."""
+        n_sys = len(self.sys_kind)
+        a, b = np.zeros(n_sys, np.int32), np.zeros(n_sys, np.int32)
+        _check(lib().mfs_plan_last_solve(self._h, a.ctypes.data_as(_i32p), b.ctypes.data_as(_i32p)),
+               "mfs_plan_last_solve")
+        return a, b
 
     def set_graph(self, enable: bool = True):
         """Replay the GMRES matvec from a captured hipGraph (see mfs.h)."""
