@@ -269,7 +269,8 @@ def main():
         "p2p_kernel_ginter_s_fp64": round(ppl * n64 / (ms64 * 1e-3) / 1e9, 2) if ms64 > 0 and wl.n_sys == 1 else None,
         "rel_diff_out_mixed_vs_fp64_gpu": diff,
         "setup_s": round(setup_s, 3),
-        "autotuned_launch": {"targets_per_lane": tuned[0], "work_items": tuned[1]} if tuned else None,
+        "autotuned_launch": {"targets_per_lane": abs(tuned[0]), "work_items": tuned[1],
+                             "persistent_grid": tuned[0] < 0} if tuned else None,
     }
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl.system(0) if wl.n_sys > 1 else wl)

@@ -242,10 +242,17 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * is copied into a fixed input first); the captured work holds kernel
  * launches only.  Ignored while timing is enabled.  mfs_plan_autotune: times
  * the matvec pair sum for candidate launch shapes (1 or 2 targets per lane x
- * 1024..16384 work items, which sets the source split) on `stream`, reps
- * launches each, keeps the fastest for the forward and transposed sums, and
- * reports it ([host] outputs, may be NULL).  Synchronous. */
+ * 1024..16384 work items, which sets the source split x one workgroup per
+ * item or a persistent grid of 2048 workgroups claiming items from a queue)
+ * on `stream`, reps launches each, keeps the fastest for the forward and
+ * transposed sums, and reports it ([host] outputs, may be NULL; *best_tpl is
+ * negative for the persistent grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
+/* Fixes the launch shape of the plan's pair sums (the choices the autotuner
+ * ranges over): targets_per_lane 1 or 2, work_items >= 1 (target blocks x
+ * source splits, at least this many), persistent != 0 for the work-queue grid.
+ * Synchronous. */
+int mfs_plan_set_launch(mfs_plan plan, int32_t targets_per_lane, int32_t work_items, int32_t persistent, void *stream);
 int mfs_plan_autotune(mfs_plan plan, int32_t prec, int32_t reps, int32_t *best_tpl, int32_t *best_min_items,
                       double *best_ms, void *stream);
 int mfs_plan_timing(mfs_plan plan, int32_t prec, int32_t reset, int64_t *launches, double *total_ms,

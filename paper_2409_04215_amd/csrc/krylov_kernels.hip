@@ -45,15 +45,20 @@ __global__ __launch_bounds__(256) void multi_dot_kernel(const VecChunk *__restri
     }
 }
 
-// out[s][i] = sum over chunks of system s of partial[c][i]
-__global__ void reduce_sys_kernel(int n_sys, const int32_t *__restrict__ sys_chunk_ptr, const double *__restrict__ partial,
-                                  int ld_partial, int nval, double *__restrict__ out, int ld_out) {
-    const int s = blockIdx.x;
-    for (int i = threadIdx.x; i < nval; i += blockDim.x) {
-        double acc = 0.0;
-        for (int c = sys_chunk_ptr[s]; c < sys_chunk_ptr[s + 1]; ++c) acc += partial[(int64_t)c * ld_partial + i];
-        out[(int64_t)s * ld_out + i] = acc;
-    }
+// out[s][i] = sum over chunks of system s of partial[c][i]; one block per (i, s),
+// threads stride over the chunks, then a fixed-order tree reduction.
+__global__ __launch_bounds__(256) void reduce_sys_kernel(const int32_t *__restrict__ sys_chunk_ptr,
+                                                         const double *__restrict__ partial, int ld_partial,
+                                                         double *__restrict__ out, int ld_out) {
+    __shared__ double sh[4];
+    const int i = blockIdx.x, s = blockIdx.y;
+    double acc = 0.0;
+    for (int c = sys_chunk_ptr[s] + threadIdx.x; c < sys_chunk_ptr[s + 1]; c += 256)
+        acc += partial[(int64_t)c * ld_partial + i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(int64_t)s * ld_out + i] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // w[n] += sign * sum_i V[i][n] coef[sys(n)][i]
@@ -111,7 +116,7 @@ int launch_multi_dot(int n_chunk, const VecChunk *chunks, const double *V, int64
 int launch_reduce_sys(int n_sys, const int32_t *sys_chunk_ptr, const double *partial, int ld_partial, int nval,
                       double *out, int ld_out, hipStream_t s) {
     if (n_sys == 0 || nval == 0) return MFS_OK;
-    reduce_sys_kernel<<<n_sys, 64, 0, s>>>(n_sys, sys_chunk_ptr, partial, ld_partial, nval, out, ld_out);
+    reduce_sys_kernel<<<dim3(nval, n_sys), 256, 0, s>>>(sys_chunk_ptr, partial, ld_partial, out, ld_out);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -119,6 +119,7 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
     for (auto &w : work) pp.items.push_back(w.it);
     pp.n_split = n_split;
     if (!pp.items.empty()) MFS_TRY(upload_vec(pp.d_items, pp.items, s));
+    MFS_TRY(pp.d_counter.reserve(sizeof(int)));
     return MFS_OK;
 }
 
@@ -362,6 +363,7 @@ struct mfs_plan_s {
     DevBuf stage;  // fixed input buffer of the captured matvec
     // autotuned pair-sum launch shape
     int tuned_tpl = 1, tuned_min_items = 2048;
+    bool tuned_persistent = false;
     // matvecs per system of the last GMRES solve, by precision
     std::vector<int32_t> last_mixed, last_fp64;
 
@@ -718,6 +720,7 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     }
     const int64_t nb = d->sys_body_ptr[d->n_sys];
     if (nb < 1) return fail(MFS_EINVAL, "no bodies");
+    if (d->n_sys > 65535) return fail(MFS_EINVAL, "at most 65535 systems per plan");
     if (!d->centre || !d->rot || !d->shape_of_body) return fail(MFS_EINVAL, "NULL body arrays");
     if (d->n_shape < 1 || !d->shape_n_src || !d->shape_n_trg || !d->shape_src || !d->shape_trg)
         return fail(MFS_EINVAL, "bad shape description");
@@ -916,7 +919,7 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     }
     // GMRES chunks (never straddle a system)
     {
-        const int64_t CH = 4096;
+        const int64_t CH = 1024;  // chunks never straddle a system; 1024 keeps 100-body solves parallel
         p->h_sys_chunk_ptr.assign(1, 0);
         for (int64_t sy = 0; sy < p->n_sys; ++sy) {
             const int64_t a = p->gam_off[p->sys_body_ptr[sy]], e = p->gam_off[p->sys_body_ptr[sy + 1]];
@@ -1351,7 +1354,10 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     MFS_TRY(launch_fill(n, 0.0, x, s));
     double *r = p->R.as<double>();
     MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // mixed plans aim a little below tol so the FP64 check passes without a restart
+    // mixed plans aim below tol: the FP64 check then passes without a restart
+    // (the GMRES estimate and the true FP64 residual agree to ~1e-7 relative),
+    // and the margin keeps the outputs within tol of the exact solution on
+    // the benchmark suspensions (at 0.8 one 10-body system ended at 1.1 tol)
     const double inner = p->prec == MFS_MIXED ? 0.5 : 1.0;
     for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
     int status = MFS_OK;
@@ -1530,37 +1536,42 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
     int btpl = p->tuned_tpl, bmi = p->tuned_min_items;
     const int tpls[2] = {1, 2};
     const int mis[5] = {1024, 2048, 4096, 8192, 16384};
+    bool bper = false;
     int status = MFS_OK;
-    for (int tpl : tpls) {
-        for (int mi : mis) {
-            P2PPlan cand;
-            status = build_p2p_items(cand, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
-                                     p->gam_off.data(), p->kind.data(), p->mu, tpl, mi, s);
-            if (status < 0) break;
-            const int64_t need = (cand.n_split > 1 ? cand.n_split : 1) * std::max<int64_t>(1, p->n_gamma);
-            if ((size_t)need * sizeof(double) > p->partial.bytes) {
-                MFS_HIP_TRY(hipStreamSynchronize(s));
-                status = grow_partial(p, need);
+    for (int per = 0; per < 2 && status >= 0; ++per) {
+        for (int tpl : tpls) {
+            for (int mi : mis) {
+                P2PPlan cand;
+                status = build_p2p_items(cand, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                                         p->gam_off.data(), p->kind.data(), p->mu, tpl, mi, s);
                 if (status < 0) break;
+                cand.persistent = per != 0;
+                const int64_t need = (cand.n_split > 1 ? cand.n_split : 1) * std::max<int64_t>(1, p->n_gamma);
+                if ((size_t)need * sizeof(double) > p->partial.bytes) {
+                    MFS_HIP_TRY(hipStreamSynchronize(s));
+                    status = grow_partial(p, need);
+                    if (status < 0) break;
+                }
+                P2PLaunch L = fwd_launch(p, prec);
+                L.skip_same = true;
+                L.out = p->ws_g64.as<double>();
+                status = launch_p2p(cand, L, s);  // warm-up
+                if (status < 0) break;
+                MFS_HIP_TRY(hipEventRecord(e0, s));
+                for (int r = 0; r < reps && status >= 0; ++r) status = launch_p2p(cand, L, s);
+                MFS_HIP_TRY(hipEventRecord(e1, s));
+                MFS_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MFS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    btpl = tpl;
+                    bmi = mi;
+                    bper = per != 0;
+                }
             }
-            P2PLaunch L = fwd_launch(p, prec);
-            L.skip_same = true;
-            L.out = p->ws_g64.as<double>();
-            status = launch_p2p(cand, L, s);  // warm-up
             if (status < 0) break;
-            MFS_HIP_TRY(hipEventRecord(e0, s));
-            for (int r = 0; r < reps && status >= 0; ++r) status = launch_p2p(cand, L, s);
-            MFS_HIP_TRY(hipEventRecord(e1, s));
-            MFS_HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            MFS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / reps < best) {
-                best = ms / reps;
-                btpl = tpl;
-                bmi = mi;
-            }
         }
-        if (status < 0) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1571,6 +1582,8 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
                             p->gam_off.data(), p->kind.data(), p->mu, btpl, bmi, s));
     MFS_TRY(build_p2p_items(p->p2p_tr, p->n_sys, p->sys_body_ptr.data(), src_row.data(), trg_row.data(),
                             p->lam_off.data(), p->kind.data(), p->mu, btpl, bmi, s));
+    p->p2p_fwd.persistent = p->p2p_tr.persistent = bper;
+    p->tuned_persistent = bper;
     MFS_HIP_TRY(hipStreamSynchronize(s));
     MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_fwd.n_split, 1) * std::max<int64_t>(1, p->n_gamma)));
     MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_tr.n_split, 1) * std::max<int64_t>(1, p->n_lambda)));
@@ -1582,7 +1595,7 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
                 g = nullptr;
             }
     MFS_HIP_TRY(hipStreamSynchronize(s));
-    if (best_tpl) *best_tpl = btpl;
+    if (best_tpl) *best_tpl = bper ? -btpl : btpl;
     if (best_min_items) *best_min_items = bmi;
     if (best_ms) *best_ms = best;
     return MFS_OK;
@@ -1595,5 +1608,33 @@ extern "C" int mfs_plan_last_solve(mfs_plan p, int32_t *mixed_matvecs, int32_t *
         if (mixed_matvecs) mixed_matvecs[sy] = have ? p->last_mixed[sy] : 0;
         if (fp64_matvecs) fp64_matvecs[sy] = have ? p->last_fp64[sy] : 0;
     }
+    return MFS_OK;
+}
+
+extern "C" int mfs_plan_set_launch(mfs_plan p, int32_t targets_per_lane, int32_t work_items, int32_t persistent,
+                                   void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (targets_per_lane != 1 && targets_per_lane != 2) return fail(MFS_EINVAL, "targets_per_lane must be 1 or 2");
+    if (work_items < 1 || work_items > (1 << 20)) return fail(MFS_EINVAL, "work_items must be in [1, 2^20]");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> src_row(p->src_row), trg_row(p->trg_row);
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    MFS_TRY(build_p2p_items(p->p2p_fwd, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
+                            p->gam_off.data(), p->kind.data(), p->mu, targets_per_lane, work_items, s));
+    MFS_TRY(build_p2p_items(p->p2p_tr, p->n_sys, p->sys_body_ptr.data(), src_row.data(), trg_row.data(),
+                            p->lam_off.data(), p->kind.data(), p->mu, targets_per_lane, work_items, s));
+    p->p2p_fwd.persistent = p->p2p_tr.persistent = persistent != 0;
+    MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_fwd.n_split, 1) * std::max<int64_t>(1, p->n_gamma)));
+    MFS_TRY(grow_partial(p, (int64_t)std::max(p->p2p_tr.n_split, 1) * std::max<int64_t>(1, p->n_lambda)));
+    for (auto &row : p->graph)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    p->tuned_tpl = targets_per_lane;
+    p->tuned_min_items = work_items;
+    p->tuned_persistent = persistent != 0;
     return MFS_OK;
 }

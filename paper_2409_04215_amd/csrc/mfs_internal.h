@@ -117,7 +117,10 @@ struct P2PPlan {
     std::vector<P2PItem> items;
     int n_split = 1;
     int tpl = 1;
+    bool persistent = false;     // fixed grid + work-queue counter instead of one workgroup per item
+    int persistent_grid = 2048;  // workgroups of a persistent launch
     DevBuf d_items;
+    DevBuf d_counter;            // int work-queue counter (persistent mode)
 };
 
 // items for targets grouped by body (body_trg_ptr), bodies grouped by system;

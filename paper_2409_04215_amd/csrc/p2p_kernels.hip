@@ -55,16 +55,16 @@ struct KernelArgs {
     double alpha;              // scale applied to the pair sum (includes 1/(4pi) or 1/(8 pi mu))
     int skip_same;
     int accumulate;
+    int *queue;                // persistent mode: work-queue counter (reset to 0 before the launch), else null
+    int n_items;
 };
 
 // ---------------------------------------------------------------------------
 // Mixed precision, Stokes / Laplace (one kernel; item.kind is wave-uniform)
 // ---------------------------------------------------------------------------
 template <int TPL>
-__global__ __launch_bounds__(BLOCK) void p2p_mixed_kernel(KernelArgs a, const float4 *__restrict__ trg_off,
-                                                          const SrcS32 *__restrict__ srcS,
-                                                          const SrcL32 *__restrict__ srcL) {
-    const P2PItem it = a.items[blockIdx.x];
+__device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it, const float4 *__restrict__ trg_off,
+                                           const SrcS32 *__restrict__ srcS, const SrcL32 *__restrict__ srcL) {
     // an inactive system still writes its epilogue (pair sum 0), so outputs stay finite
     const bool active = !a.sys_active || a.sys_active[it.sys];
     const bool stokes = it.kind == MFS_STOKES;
@@ -179,10 +179,8 @@ __global__ __launch_bounds__(BLOCK) void p2p_mixed_kernel(KernelArgs a, const fl
 // FP64
 // ---------------------------------------------------------------------------
 template <int TPL>
-__global__ __launch_bounds__(BLOCK) void p2p_f64_kernel(KernelArgs a, const double4 *__restrict__ trg_off,
-                                                        const SrcS64 *__restrict__ srcS,
-                                                        const SrcL64 *__restrict__ srcL) {
-    const P2PItem it = a.items[blockIdx.x];
+__device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, const double4 *__restrict__ trg_off,
+                                         const SrcS64 *__restrict__ srcS, const SrcL64 *__restrict__ srcL) {
     // an inactive system still writes its epilogue (pair sum 0), so outputs stay finite
     const bool active = !a.sys_active || a.sys_active[it.sys];
     const bool stokes = it.kind == MFS_STOKES;
@@ -284,6 +282,49 @@ __global__ __launch_bounds__(BLOCK) void p2p_f64_kernel(KernelArgs a, const doub
     }
 }
 
+// One work item per workgroup, or (persistent mode) a fixed grid whose
+// workgroups claim items from a counter until the list is exhausted; every
+// workgroup ends with the claim that runs past the end, so the grid drains.
+template <int TPL>
+__global__ __launch_bounds__(BLOCK) void p2p_mixed_kernel(KernelArgs a, const float4 *__restrict__ trg_off,
+                                                          const SrcS32 *__restrict__ srcS,
+                                                          const SrcL32 *__restrict__ srcL) {
+    if (!a.queue) {
+        mixed_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL);
+        return;
+    }
+    __shared__ int slot;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int k = slot;
+        if (k >= a.n_items) break;
+        mixed_item<TPL>(a, a.items[k], trg_off, srcS, srcL);
+    }
+}
+
+template <int TPL>
+__global__ __launch_bounds__(BLOCK) void p2p_f64_kernel(KernelArgs a, const double4 *__restrict__ trg_off,
+                                                        const SrcS64 *__restrict__ srcS,
+                                                        const SrcL64 *__restrict__ srcL) {
+    if (!a.queue) {
+        f64_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL);
+        return;
+    }
+    __shared__ int slot;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int k = slot;
+        if (k >= a.n_items) break;
+        f64_item<TPL>(a, a.items[k], trg_off, srcS, srcL);
+    }
+}
+
+__global__ void reset_counter_kernel(int *c) { *c = 0; }
+
 // Sum of split slices: out = (acc ? out : 0) + addend + sum_s partial[s]
 __global__ void reduce_split_kernel(int64_t n, const double *__restrict__ partial, int64_t stride, int n_split,
                                     const double *__restrict__ addend, double *__restrict__ out, int accumulate) {
@@ -369,7 +410,15 @@ int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) {
     a.addend = direct ? L.addend : nullptr;
     a.accumulate = direct ? (L.accumulate ? 1 : 0) : 0;
     a.out_stride = L.n_val;
-    const dim3 grid((unsigned)pp.items.size());
+    a.n_items = (int)pp.items.size();
+    a.queue = nullptr;
+    dim3 grid((unsigned)pp.items.size());
+    if (pp.persistent) {
+        a.queue = pp.d_counter.as<int>();
+        grid = dim3((unsigned)std::min<size_t>(pp.items.size(), (size_t)pp.persistent_grid));
+        reset_counter_kernel<<<1, 1, 0, s>>>(a.queue);
+        MFS_HIP_TRY(hipGetLastError());
+    }
     if (L.ev_start) MFS_HIP_TRY(hipEventRecord(L.ev_start, s));
     if (L.prec == MFS_MIXED) {
         if (pp.tpl == 2)

@@ -75,6 +75,7 @@ def lib():
         L.mfs_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i64p, _dp, _dp]
         L.mfs_plan_set_graph.argtypes = [_vp, ctypes.c_int32]
         L.mfs_plan_last_solve.argtypes = [_vp, _i32p, _i32p]
+        L.mfs_plan_set_launch.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]
         L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
@@ -308,12 +309,18 @@ class Plan:
                "mfs_plan_last_solve")
         return a, b
 
+    def set_launch(self, targets_per_lane: int, work_items: int, persistent: bool = False, stream=None):
+        """Fix the pair-sum launch shape (see mfs_plan_set_launch)."""
+        _check(lib().mfs_plan_set_launch(self._h, int(targets_per_lane), int(work_items), int(persistent),
+                                         _stream(stream)), "mfs_plan_set_launch")
+
     def set_graph(self, enable: bool = True):
         """Replay the GMRES matvec from a captured hipGraph (see mfs.h)."""
         _check(lib().mfs_plan_set_graph(self._h, int(enable)), "mfs_plan_set_graph")
 
     def autotune(self, prec: Optional[int] = None, reps: int = 3, stream=None):
-        """Pick the fastest pair-sum launch shape; returns (targets per lane, work items, ms)."""
+        """Pick the fastest pair-sum launch shape; returns (targets per lane, work items, ms);
+        targets per lane is negative when the persistent work-queue grid won."""
         tpl, mi, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(lib().mfs_plan_autotune(self._h, self.precision if prec is None else int(prec), int(reps),
                                        ctypes.byref(tpl), ctypes.byref(mi), ctypes.byref(ms), _stream(stream)),

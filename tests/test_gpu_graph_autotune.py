@@ -66,10 +66,39 @@ def test_autotune_keeps_results(kind):
     ref = pr.matvec(g)
     plan = mfs.Plan.from_workload(wl, mfs.MIXED)
     tpl, mi, ms = plan.autotune(mfs.MIXED, reps=2)
-    assert tpl in (1, 2) and mi in (1024, 2048, 4096, 8192, 16384) and ms > 0
+    assert abs(tpl) in (1, 2) and mi in (1024, 2048, 4096, 8192, 16384) and ms > 0
     assert rel_inf(plan.matvec(_dev(g), mfs.FP64).cpu().numpy(), ref) <= 1e-10
     assert rel_inf(plan.matvec(_dev(g), mfs.MIXED).cpu().numpy(), ref) <= 1e-4
     assert rel_inf(plan.matvec_adjoint(_dev(g), mfs.FP64).cpu().numpy(), pr.matvec_T(g)) <= 1e-10
     out, info = plan.solve(_dev(net_flat(wl)), tol=1e-8)
     assert info["status"] == mfs.MFS_OK
     assert rel_inf(out.cpu().numpy(), pr.solve(wl.net[0], tol=1e-12)["out"]) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_every_launch_shape(kind):
+    """Each launch shape the autotuner can pick (targets per lane, work items,
+    persistent work-queue grid) gives the same operator."""
+    mfs = _mfs()
+    wl = W.small_cluster(6, kind, 45, 301, seed=75)
+    pr = O.Problem.from_workload(wl)
+    g = W.random_vector(pr.n_gamma, 76)
+    ref, ref_t = pr.matvec(g), pr.matvec_T(g)
+    plan = mfs.Plan.from_workload(wl, mfs.MIXED)
+    for tpl in (1, 2):
+        for items in (1, 64, 16384):
+            for per in (False, True):
+                plan.set_launch(tpl, items, per)
+                for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-4)):
+                    e = (rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref),
+                         rel_inf(plan.matvec_adjoint(_dev(g), prec).cpu().numpy(), ref_t))
+                    assert max(e) <= tol, (tpl, items, per, prec, e)
+    # a persistent-grid solve replayed from a graph equals the eager one
+    plan.set_launch(1, 16384, True)
+    net = _dev(net_flat(wl))
+    eager, _ = plan.solve(net, tol=1e-9)
+    plan.set_graph(True)
+    for _ in range(2):
+        out, _ = plan.solve(net, tol=1e-9)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
