@@ -64,7 +64,7 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
                     int tpl, int min_items, hipStream_t s) {
     pp.items.clear();
     pp.tpl = tpl;
-    const int blk = 256 * tpl;
+    const int blk = 64 * tpl;  // targets per item: 64 lanes x tpl (the pair kernels' item shape)
     // bodies per source chunk: the largest chunk (fewest split slices) that still
     // gives at least min_items items.
     auto count_items = [&](int64_t chunk) {

@@ -14,9 +14,11 @@
 // on the transposed orientation (lanes = proxies with s, sources = collocation
 // points with w) gives dPhi/dy_j = -sum_i dPhi_ij/dd directly.
 //
-// The walk is the one of the forward sum: wave-uniform source loop (scalar
-// loads, SGPR operands), one lane per point, same-body handling and mixed
-// FP32-pair / FP64-accumulation precision exactly as there.
+// The walk is the one of the forward sum: an item of 64 lane points, the four
+// waves of the workgroup each taking a contiguous quarter of every source body
+// (wave-uniform loop, scalar loads, SGPR operands), the partial gradients added
+// in wave order through LDS, same-body handling and mixed FP32-pair /
+// FP64-accumulation precision exactly as there.
 #include "mfs_internal.h"
 
 namespace mfs {
@@ -24,6 +26,7 @@ namespace mfs {
 namespace {
 
 constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / 64;
 constexpr int FLUSH = 64;
 
 __device__ __forceinline__ double rsqrt_f64(double r2) {
@@ -56,10 +59,13 @@ __global__ __launch_bounds__(BLOCK) void p2p_grad_kernel(GradArgs a, const void 
                                                          const void *__restrict__ srcS_v,
                                                          const void *__restrict__ srcL_v) {
     typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ double lds[(WAVES - 1) * 3 * 64];
     const P2PItem it = a.items[blockIdx.x];
     const bool stokes = it.kind == MFS_STOKES;
     const int dim = stokes ? 3 : 1;
-    const int i = it.t0 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = it.t0 + lane;
     const bool valid = i < it.t1;
     const int ii = valid ? i : it.t0;
     const int body = a.lane_body[ii];
@@ -84,7 +90,10 @@ __global__ __launch_bounds__(BLOCK) void p2p_grad_kernel(GradArgs a, const void 
         if (!__any(use)) continue;
         R xr[3];
         for (int c = 0; c < 3; ++c) xr[c] = xt[c] + (R)(ct[c] - a.centre[3 * b + c]);
-        const int j0 = a.src_ptr[b], j1 = a.src_ptr[b + 1];
+        // this wave's contiguous quarter of the body's sources
+        const int s0 = a.src_ptr[b], s1 = a.src_ptr[b + 1];
+        const int qn = (s1 - s0 + WAVES - 1) / WAVES;
+        const int j0 = min(s0 + wv * qn, s1), j1 = min(j0 + qn, s1);
         for (int jb = j0; jb < j1; jb += FLUSH) {
             const int je = min(jb + FLUSH, j1);
             R p0 = 0, p1 = 0, p2 = 0;
@@ -143,6 +152,13 @@ __global__ __launch_bounds__(BLOCK) void p2p_grad_kernel(GradArgs a, const void 
             acc[2] += use ? (double)p2 : 0.0;
         }
     }
+    // waves 1..3 hand their partial gradients to wave 0, which adds them in wave order
+    if (wv > 0)
+        for (int c = 0; c < 3; ++c) lds[((wv - 1) * 3 + c) * 64 + lane] = acc[c];
+    __syncthreads();
+    if (wv > 0) return;
+    for (int w = 1; w < WAVES; ++w)
+        for (int c = 0; c < 3; ++c) acc[c] += lds[((w - 1) * 3 + c) * 64 + lane];
     if (!valid) return;
     double *out = a.out + (int64_t)it.split * a.out_stride + 3 * (int64_t)i;
     for (int c = 0; c < 3; ++c) {
@@ -167,6 +183,7 @@ __global__ void reduce3_kernel(int64_t n, const double *__restrict__ partial, in
 // lane vectors `lane_vec` indexed in the items' output layout; gradient out [n_lane][3]
 int launch_p2p_grad(const P2PPlan &pp, const P2PLaunch &L, const double *lane_vec, int64_t n_lane, hipStream_t s) {
     if (pp.items.empty()) return MFS_OK;
+    if (pp.tpl != 1) return fail(MFS_EINVAL, "gradient pair sums take items of one target per lane");
     GradArgs a;
     a.items = pp.d_items.as<P2PItem>();
     a.centre = L.centre;

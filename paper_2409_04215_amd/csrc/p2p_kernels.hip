@@ -5,14 +5,20 @@
 //          u_i = sum_j (s_j + (d.s_j) d / r^2) / (8 pi mu r),  d = x_i - y_j
 //
 // Design (MI355X):
-//  * One work item = a block of targets of one system x a range of source
-//    bodies of the same system.  Items are launched largest-first, so the
-//    hardware dispatcher hands the long items out before the short ones.
+//  * One work item = a block of 64*TPL targets of one system x a range of
+//    source bodies of the same system, run by one workgroup of four waves.
+//    Every wave holds all the item's targets (TPL per lane, register blocking)
+//    and takes a contiguous quarter of each source body; the four FP64
+//    partial sums meet in LDS once per item and are added in wave order, so
+//    results do not depend on timing.  Splitting the sources rather than the
+//    targets keeps items small in targets, so a launch reaches many items
+//    with few source splits (each split costs one FP64 slice of the output).
+//  * Items are launched largest-first, so the hardware dispatcher hands the
+//    long items out before the short ones.
 //  * Sources are read with wave-uniform addresses: every lane of a wave walks
 //    the same source list, so the compiler turns the reads into scalar loads
 //    (s_load) and the VALU instructions take the source coordinates and
-//    strengths as SGPR operands.  No LDS and no barriers are needed.
-//  * Each lane owns TPL targets (register blocking for ILP).
+//    strengths as SGPR operands.
 //  * Mixed precision: the coordinates are split into a per-body FP64 centre
 //    and a small FP32 offset; per (lane, source body) the FP64 centre
 //    difference is rounded to FP32 once, so the FP32 rounding of d scales
@@ -32,7 +38,53 @@ namespace mfs {
 namespace {
 
 constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / 64;
 constexpr int FLUSH = 64;
+
+// Adds the FP64 accumulators of waves 1..WAVES-1 into wave 0's, in wave order.
+// lds holds (WAVES-1) * NV * 64 doubles.  Every thread of the workgroup must
+// call it; returns true in wave 0, which then owns the sums.
+template <int NV>
+__device__ __forceinline__ bool reduce_waves(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wv > 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[((wv - 1) * NV + q) * 64 + lane] = v[q];
+    __syncthreads();
+    if (wv > 0) return false;
+    for (int w = 1; w < WAVES; ++w)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += lds[((w - 1) * NV + q) * 64 + lane];
+    return true;
+}
+
+struct Src4 {
+    SrcS32 s[4];
+};
+
+// One Stokes source against the lane's TPL targets, FP32 (eq. (stokeslet) without 1/(8 pi mu)).
+template <int TPL>
+__device__ __forceinline__ void stokes_pair(const float (&xr)[TPL][3], const float4 y, const float4 f,
+                                            float (&p)[TPL][3]) {
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const float d0 = xr[t][0] - y.x, d1 = xr[t][1] - y.y, d2 = xr[t][2] - y.z;
+        const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float df = __builtin_fmaf(d2, f.z, __builtin_fmaf(d1, f.y, d0 * f.x));
+        const float sc = df * (ri * ri);
+        p[t][0] = __builtin_fmaf(ri, __builtin_fmaf(sc, d0, f.x), p[t][0]);
+        p[t][1] = __builtin_fmaf(ri, __builtin_fmaf(sc, d1, f.y), p[t][1]);
+        p[t][2] = __builtin_fmaf(ri, __builtin_fmaf(sc, d2, f.z), p[t][2]);
+    }
+}
+
+// This wave's contiguous quarter [j0, j1) of the source range [b0, b1).
+__device__ __forceinline__ void wave_range(int b0, int b1, int wv, int &j0, int &j1) {
+    const int q = (b1 - b0 + WAVES - 1) / WAVES;
+    j0 = min(b0 + wv * q, b1);
+    j1 = min(j0 + q, b1);
+}
 
 __device__ __forceinline__ double rsqrt_f64(double r2) {
     double y = __builtin_amdgcn_rsq(r2);
@@ -64,10 +116,13 @@ struct KernelArgs {
 // ---------------------------------------------------------------------------
 template <int TPL>
 __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it, const float4 *__restrict__ trg_off,
-                                           const SrcS32 *__restrict__ srcS, const SrcL32 *__restrict__ srcL) {
+                                           const SrcS32 *__restrict__ srcS, const SrcL32 *__restrict__ srcL,
+                                           double *lds) {
     // an inactive system still writes its epilogue (pair sum 0), so outputs stay finite
     const bool active = !a.sys_active || a.sys_active[it.sys];
     const bool stokes = it.kind == MFS_STOKES;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     int idx[TPL];
     bool valid[TPL];
@@ -77,7 +132,7 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
     double acc[TPL][3];
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
-        idx[t] = it.t0 + threadIdx.x + t * BLOCK;
+        idx[t] = it.t0 + lane + t * 64;
         valid[t] = idx[t] < it.t1;
         const int i = valid[t] ? idx[t] : it.t0;
         body[t] = a.trg_body[i];
@@ -108,29 +163,24 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
             xr[t][1] = xt[t][1] + (float)(ct[t][1] - cs1);
             xr[t][2] = xt[t][2] + (float)(ct[t][2] - cs2);
         }
-        const int j0 = a.src_ptr[b], j1 = a.src_ptr[b + 1];
+        int j0, j1;
+        wave_range(a.src_ptr[b], a.src_ptr[b + 1], wv, j0, j1);
         if (stokes) {
             for (int jb = j0; jb < j1; jb += FLUSH) {
                 const int je = min(jb + FLUSH, j1);
                 float p[TPL][3];
 #pragma unroll
                 for (int t = 0; t < TPL; ++t) p[t][0] = p[t][1] = p[t][2] = 0.f;
-#pragma unroll 4
-                for (int j = jb; j < je; ++j) {
-                    const float4 y = srcS[j].pos;
-                    const float4 f = srcS[j].str;
+                // four sources per 128-byte scalar load (s_load_dwordx16 pairs), then the tail
+                const SrcS32 *__restrict__ ps = srcS + jb;
+                const int n = je - jb;
+                int k = 0;
+                for (; k + 4 <= n; k += 4) {
+                    const Src4 q = *reinterpret_cast<const Src4 *>(ps + k);
 #pragma unroll
-                    for (int t = 0; t < TPL; ++t) {
-                        const float d0 = xr[t][0] - y.x, d1 = xr[t][1] - y.y, d2 = xr[t][2] - y.z;
-                        const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
-                        const float ri = __builtin_amdgcn_rsqf(r2);
-                        const float df = __builtin_fmaf(d2, f.z, __builtin_fmaf(d1, f.y, d0 * f.x));
-                        const float s = df * (ri * ri);
-                        p[t][0] = __builtin_fmaf(ri, __builtin_fmaf(s, d0, f.x), p[t][0]);
-                        p[t][1] = __builtin_fmaf(ri, __builtin_fmaf(s, d1, f.y), p[t][1]);
-                        p[t][2] = __builtin_fmaf(ri, __builtin_fmaf(s, d2, f.z), p[t][2]);
-                    }
+                    for (int u = 0; u < 4; ++u) stokes_pair<TPL>(xr, q.s[u].pos, q.s[u].str, p);
                 }
+                for (; k < n; ++k) stokes_pair<TPL>(xr, ps[k].pos, ps[k].str, p);
 #pragma unroll
                 for (int t = 0; t < TPL; ++t) {
                     acc[t][0] += use[t] ? (double)p[t][0] : 0.0;
@@ -144,9 +194,10 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
                 float p[TPL];
 #pragma unroll
                 for (int t = 0; t < TPL; ++t) p[t] = 0.f;
+const SrcL32 *__restrict__ ps = srcL + jb;
 #pragma unroll 8
-                for (int j = jb; j < je; ++j) {
-                    const float4 y = srcL[j];
+                for (int k = 0; k < je - jb; ++k) {
+                    const float4 y = ps[k];
 #pragma unroll
                     for (int t = 0; t < TPL; ++t) {
                         const float d0 = xr[t][0] - y.x, d1 = xr[t][1] - y.y, d2 = xr[t][2] - y.z;
@@ -160,6 +211,12 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
         }
     }
 
+    double sum[TPL * 3];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sum[3 * t + c] = acc[t][c];
+    if (!reduce_waves<TPL * 3>(sum, lds)) return;
     const int dim = stokes ? 3 : 1;
     double *out = a.out + (int64_t)it.split * a.out_stride;
 #pragma unroll
@@ -167,7 +224,7 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
         if (!valid[t]) continue;
         const int64_t o = it.out0 + (int64_t)dim * (idx[t] - it.t0);
         for (int c = 0; c < dim; ++c) {
-            double v = a.alpha * it.scale * acc[t][c];
+            double v = a.alpha * it.scale * sum[3 * t + c];
             if (a.addend) v += a.addend[o + c];
             if (a.accumulate) v += out[o + c];
             out[o + c] = v;
@@ -180,10 +237,13 @@ __device__ __forceinline__ void mixed_item(const KernelArgs &a, const P2PItem it
 // ---------------------------------------------------------------------------
 template <int TPL>
 __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, const double4 *__restrict__ trg_off,
-                                         const SrcS64 *__restrict__ srcS, const SrcL64 *__restrict__ srcL) {
+                                         const SrcS64 *__restrict__ srcS, const SrcL64 *__restrict__ srcL,
+                                         double *lds) {
     // an inactive system still writes its epilogue (pair sum 0), so outputs stay finite
     const bool active = !a.sys_active || a.sys_active[it.sys];
     const bool stokes = it.kind == MFS_STOKES;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     int idx[TPL];
     bool valid[TPL];
@@ -193,7 +253,7 @@ __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, 
     double acc[TPL][3];
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
-        idx[t] = it.t0 + threadIdx.x + t * BLOCK;
+        idx[t] = it.t0 + lane + t * 64;
         valid[t] = idx[t] < it.t1;
         const int i = valid[t] ? idx[t] : it.t0;
         body[t] = a.trg_body[i];
@@ -224,14 +284,16 @@ __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, 
             xr[t][1] = xt[t][1] + (ct[t][1] - cs1);
             xr[t][2] = xt[t][2] + (ct[t][2] - cs2);
         }
-        const int j0 = a.src_ptr[b], j1 = a.src_ptr[b + 1];
+        int j0, j1;
+        wave_range(a.src_ptr[b], a.src_ptr[b + 1], wv, j0, j1);
         double p[TPL][3];
 #pragma unroll
         for (int t = 0; t < TPL; ++t) p[t][0] = p[t][1] = p[t][2] = 0.0;
         if (stokes) {
+const SrcS64 *__restrict__ ps = srcS + j0;
 #pragma unroll 2
-            for (int j = j0; j < j1; ++j) {
-                const SrcS64 &sj = srcS[j];
+            for (int k = 0; k < j1 - j0; ++k) {
+                const SrcS64 &sj = ps[k];
                 const double y0 = sj.pos[0], y1 = sj.pos[1], y2 = sj.pos[2];
                 const double f0 = sj.str[0], f1 = sj.str[1], f2 = sj.str[2];
 #pragma unroll
@@ -247,9 +309,10 @@ __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, 
                 }
             }
         } else {
+const SrcL64 *__restrict__ ps = srcL + j0;
 #pragma unroll 4
-            for (int j = j0; j < j1; ++j) {
-                const SrcL64 &sj = srcL[j];
+            for (int k = 0; k < j1 - j0; ++k) {
+                const SrcL64 &sj = ps[k];
                 const double y0 = sj.v[0], y1 = sj.v[1], y2 = sj.v[2], q = sj.v[3];
 #pragma unroll
                 for (int t = 0; t < TPL; ++t) {
@@ -267,6 +330,12 @@ __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, 
         }
     }
 
+    double sum[TPL * 3];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sum[3 * t + c] = acc[t][c];
+    if (!reduce_waves<TPL * 3>(sum, lds)) return;
     const int dim = stokes ? 3 : 1;
     double *out = a.out + (int64_t)it.split * a.out_stride;
 #pragma unroll
@@ -274,7 +343,7 @@ __device__ __forceinline__ void f64_item(const KernelArgs &a, const P2PItem it, 
         if (!valid[t]) continue;
         const int64_t o = it.out0 + (int64_t)dim * (idx[t] - it.t0);
         for (int c = 0; c < dim; ++c) {
-            double v = a.alpha * it.scale * acc[t][c];
+            double v = a.alpha * it.scale * sum[3 * t + c];
             if (a.addend) v += a.addend[o + c];
             if (a.accumulate) v += out[o + c];
             out[o + c] = v;
@@ -289,18 +358,19 @@ template <int TPL>
 __global__ __launch_bounds__(BLOCK) void p2p_mixed_kernel(KernelArgs a, const float4 *__restrict__ trg_off,
                                                           const SrcS32 *__restrict__ srcS,
                                                           const SrcL32 *__restrict__ srcL) {
+    __shared__ double lds[(WAVES - 1) * 3 * TPL * 64];
     if (!a.queue) {
-        mixed_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL);
+        mixed_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL, lds);
         return;
     }
     __shared__ int slot;
     for (;;) {
-        __syncthreads();
+        __syncthreads();  // also orders the previous item's LDS reads before the next item's writes
         if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
         __syncthreads();
         const int k = slot;
         if (k >= a.n_items) break;
-        mixed_item<TPL>(a, a.items[k], trg_off, srcS, srcL);
+        mixed_item<TPL>(a, a.items[k], trg_off, srcS, srcL, lds);
     }
 }
 
@@ -308,18 +378,19 @@ template <int TPL>
 __global__ __launch_bounds__(BLOCK) void p2p_f64_kernel(KernelArgs a, const double4 *__restrict__ trg_off,
                                                         const SrcS64 *__restrict__ srcS,
                                                         const SrcL64 *__restrict__ srcL) {
+    __shared__ double lds[(WAVES - 1) * 3 * TPL * 64];
     if (!a.queue) {
-        f64_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL);
+        f64_item<TPL>(a, a.items[blockIdx.x], trg_off, srcS, srcL, lds);
         return;
     }
     __shared__ int slot;
     for (;;) {
-        __syncthreads();
+        __syncthreads();  // also orders the previous item's LDS reads before the next item's writes
         if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
         __syncthreads();
         const int k = slot;
         if (k >= a.n_items) break;
-        f64_item<TPL>(a, a.items[k], trg_off, srcS, srcL);
+        f64_item<TPL>(a, a.items[k], trg_off, srcS, srcL, lds);
     }
 }
 
