@@ -65,10 +65,11 @@ def _pairs_per_system(wl):
     return out
 
 
-def _counter_traffic(workload: str):
-    """HBM bytes per launch of the pair kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), or None when the
-    kernel source has changed since the counters were taken."""
+def _counter_traffic(workload: str, shape):
+    """HBM bytes per launch of the pair kernel at launch shape `shape` (targets
+    per lane, work items, persistent) from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-kernel calibrated), or None when the kernel source
+    has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"p2p_mixed_stokes_{workload}_pmc.txt")
     src = os.path.join(ROOT, "paper_2409_04215_amd", "csrc", "p2p_kernels.hip")
@@ -81,7 +82,10 @@ def _counter_traffic(workload: str):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if not rec or rec.get("source_sha256_16") != sha:
         return None
-    return rec
+    for r in rec.get("per_shape", []):
+        if tuple(r["launch"]) == tuple(shape):
+            return r
+    return None
 
 
 def _timed_solves(plan, net, tol, steps, torch):
@@ -127,6 +131,30 @@ def cpu_baseline(wl, budget_s: float = 15.0):
                 seconds=dt)
 
 
+# (targets per lane, work items, persistent grid): the autotuner's candidates
+LAUNCH_SHAPES = [(tpl, items, per) for per in (0, 1) for tpl in (1, 2) for items in (1024, 2048, 4096, 8192, 16384)]
+
+
+def counter_sweep(plan, mfs, torch, np):
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)  # one elementwise kernel that reads and writes 1 GiB
+    torch.cuda.synchronize()
+    del a, b
+    g = torch.tensor(np.random.default_rng(3).standard_normal(plan.n_gamma), dtype=torch.float64, device="cuda")
+    for tpl, items, per in LAUNCH_SHAPES:
+        plan.set_launch(tpl, items, bool(per))
+        plan.matvec(g, mfs.MIXED)
+        torch.cuda.synchronize()
+    plan.set_launch(1, 16384, False)
+    plan.matvec(g, mfs.FP64)  # one FP64 matvec for the FP64 pair-kernel counters
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_sweep": LAUNCH_SHAPES, "fp64_matvec_shape": [1, 16384, 0],
+                      "calib_copy_bytes": 1 << 30}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,8 +167,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pair-sum launch shape")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run one device copy of this size (counter calibration runs)")
+    ap.add_argument("--counter-sweep", action="store_true",
+                    help="for rocprofv3 counter runs: one 1 GiB copy (calibration), one mixed matvec per "
+                         "pair-sum launch shape the autotuner can pick (LAUNCH_SHAPES order), then one FP64 "
+                         "matvec; prints the shapes")
+    ap.add_argument("--launch", default=None,
+                    help="fix the pair-sum launch shape instead of autotuning: TPL,WORK_ITEMS,PERSISTENT "
+                         "(e.g. 1,16384,0; used for counter runs, which must repeat one shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -163,10 +196,17 @@ def main():
     plan_mx = mfs.Plan.from_workload(wl, mfs.MIXED)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    if args.counter_sweep:
+        return counter_sweep(plan_mx, mfs, torch, np)
     plan_64 = mfs.Plan.from_workload(wl, mfs.FP64)
 
     tuned = None
-    if not args.no_autotune:
+    if args.launch:
+        tpl, items, per = (int(v) for v in args.launch.split(","))
+        for p in (plan_mx, plan_64):
+            p.set_launch(tpl, items, bool(per))
+        tuned = (-tpl if per else tpl, items, float("nan"))
+    elif not args.no_autotune:
         tuned = plan_mx.autotune(mfs.MIXED, reps=3)
         plan_64.autotune(mfs.FP64, reps=2)
 
@@ -217,14 +257,9 @@ def main():
     plan_64.set_timing(False)
     diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
 
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads and writes calib_copy_mib MiB
-        torch.cuda.synchronize()
-
-    traffic = _counter_traffic(args.workload) if args.workload == "ellipsoids_100" and kind == 1 else None
+    shape = (abs(tuned[0]), tuned[1], int(tuned[0] < 0)) if tuned else (1, 2048, 0)
+    traffic = (_counter_traffic(args.workload, shape)
+               if args.workload == "ellipsoids_100" and kind == 1 else None)
     avg_ms = ms_mx / max(n_mx, 1)
     achieved = tot_flops / (ms_mx * 1e-3) / 1e12 if ms_mx > 0 else 0.0
     flops_per_pair = tot_flops / max(tot_pairs_mx, 1.0)
