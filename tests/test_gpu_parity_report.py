@@ -1,0 +1,157 @@
+"""Every output of the hot path against the FP64 oracle, in both precisions,
+gathered into one table (printed with pytest -s; also written to the file
+named by the environment variable MFS_PARITY_REPORT when it is set).
+
+Case: one cluster per kind of 6 prolate spheroids (1,1,2), N=45 proxies,
+M=301 collocation points per body (ragged 64-target blocks, several GEMM
+tiles); random unit-normal inputs for the operator pieces, N(0,1) net
+forces/torques or charges for the solves.  rel_inf = max|x - ref| / max|ref|
+over the stacked output.  Bars (the same as the per-entry-point tests):
+
+  output                         FP64      MIXED
+  pair sum u (standalone)        1e-12     2e-5   FP32 pairs, runs of <=64 summed in FP32, FP64 accumulation
+  backward pair sums (ds, dx, dy) 1e-11    5e-5
+  completion strengths s0        1e-13     1e-13  FP64 on both paths
+  right-hand side b              1e-12     2e-5   one all-pairs sum
+  S_L^+ apply, (I-L) S_L^+ apply 1e-10     5e-3   FP32 factors: u32 * cond(S_L) on a random input
+  A gamma, A^T w                 1e-10     1e-4   the off-body sums damp the rough part again
+  gamma, lambda, sigma (solve)   1e-8      1e-3   FP64 solve at tol 1e-10; mixed at tol 1e-5
+  U or phi (solve)               1e-8      1e-5   the outputs the method reports
+  dJ/dc (adjoint, Stokes)        1e-8      1e-5   J = sum |U|^2; FP64 tol 1e-12, mixed tol 1e-8
+
+The oracle's solves run at tol 1e-12.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import net_flat, rel_inf, structure
+
+pytestmark = pytest.mark.gpu
+
+BARS = {
+    "pair sum u": (1e-12, 2e-5),
+    "backward pair sums": (1e-11, 5e-5),
+    "completion s0": (1e-13, 1e-13),
+    "rhs b": (1e-12, 2e-5),
+    "S_L^+ apply": (1e-10, 5e-3),
+    "(I-L) S_L^+ apply": (1e-10, 5e-3),
+    "A gamma": (1e-10, 1e-4),
+    "A^T w": (1e-10, 1e-4),
+    "gamma": (1e-8, 1e-3),
+    "lambda": (1e-8, 1e-3),
+    "sigma": (1e-8, 1e-3),
+    "U / phi": (1e-8, 1e-5),
+    "dJ/dc": (1e-8, 1e-5),
+}
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _rows(kind):
+    mfs = _mfs()
+    wl = W.small_cluster(6, kind, 45, 301, seed=91)
+    pr = O.Problem.from_workload(wl)
+    dim = 3 if kind == W.STOKES else 1
+    rows = []
+
+    def add(name, prec, err):
+        rows.append((name, "stokes" if kind == W.STOKES else "laplace", "fp64" if prec == mfs.FP64 else "mixed",
+                     err, BARS[name][0 if prec == mfs.FP64 else 1]))
+
+    # standalone pair sums and their backward
+    sp, tp, pp = structure(wl)
+    X, tb = wl.world_points("trg")
+    Y, sb = wl.world_points("src")
+    rng = np.random.default_rng(92)
+    s = rng.standard_normal((Y.shape[0], dim)).squeeze()
+    w = rng.standard_normal((X.shape[0], dim)).squeeze()
+    ref_u = O.p2p(kind, X, tb, Y, sb, s, 1.0, True)
+    ref_gs = O.p2p(kind, Y, sb, X, tb, w, 1.0, True)
+    ref_gx, ref_gy = O.p2p_grad(kind, X, tb, w, Y, sb, s, 1.0, True)
+    fwd = mfs.p2p_stokes if kind == W.STOKES else mfs.p2p_laplace
+    bwd = mfs.p2p_stokes_backward if kind == W.STOKES else mfs.p2p_laplace_backward
+    for prec in (mfs.FP64, mfs.MIXED):
+        if kind == W.STOKES:
+            u = fwd(sp, tp, pp, _dev(X).view(-1, 3), _dev(Y).view(-1, 3), _dev(s).view(-1, 3), 1.0,
+                    mfs.SKIP_SAME_BODY, prec)
+        else:
+            u = fwd(sp, tp, pp, _dev(X).view(-1, 3), _dev(Y).view(-1, 3), _dev(s), mfs.SKIP_SAME_BODY, prec)
+        add("pair sum u", prec, rel_inf(_np(u), ref_u))
+        gs, gx, gy = bwd(sp, tp, pp, _dev(X).view(-1, 3), _dev(Y).view(-1, 3),
+                         _dev(s).view(-1, 3) if kind == W.STOKES else _dev(s),
+                         _dev(w).view(-1, 3) if kind == W.STOKES else _dev(w), prec=prec)
+        add("backward pair sums", prec, max(rel_inf(_np(gs), ref_gs), rel_inf(_np(gx), ref_gx),
+                                            rel_inf(_np(gy), ref_gy)))
+
+    # operator pieces
+    net = _dev(net_flat(wl))
+    b_ref, s0_ref = pr.rhs(wl.net[0])
+    g = W.random_vector(pr.n_gamma, 93)
+    v = W.random_vector(pr.n_gamma, 94)
+    ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
+    ref_pp = pr.precondition(g)
+    ref_A, ref_AT = pr.matvec(g), pr.matvec_T(v)
+    sol = pr.solve(wl.net[0], tol=1e-12)
+    for prec in (mfs.FP64, mfs.MIXED):
+        plan = mfs.Plan.from_workload(wl, prec)
+        b, s0 = plan.rhs(net, prec=prec)
+        add("completion s0", prec, rel_inf(_np(s0), s0_ref))
+        add("rhs b", prec, rel_inf(_np(b), b_ref))
+        add("S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), ref_p))
+        add("(I-L) S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), mfs.PROJECT, prec)), ref_pp))
+        add("A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), ref_A))
+        add("A^T w", prec, rel_inf(_np(plan.matvec_adjoint(_dev(v), prec)), ref_AT))
+        out, info = plan.solve(net, tol=1e-10 if prec == mfs.FP64 else 1e-5)
+        assert info["status"] == mfs.MFS_OK
+        out2, sigma = plan.extract(info["gamma"], info["s0"], want_sigma=True)
+        add("gamma", prec, rel_inf(_np(info["gamma"]), sol["gamma"]))
+        add("sigma", prec, rel_inf(_np(sigma), sol["sigma"]))
+        add("U / phi", prec, rel_inf(_np(out), sol["out"]))
+        assert torch.equal(out, out2)
+        # lambda = S_L^+ gamma with the FP64 factors (the extraction's own step)
+        lam = plan.precond_apply(info["gamma"], 0, mfs.FP64)
+        add("lambda", prec, rel_inf(_np(lam), sol["lam"]))
+        plan.close()
+
+    # adjoint gradient of J = sum |U|^2 with respect to the centres
+    if kind == W.STOKES:
+        _, g_ref, _ = pr.velocity_loss_gradient(wl.net[0], tol=1e-12)
+        for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
+            plan = mfs.Plan.from_workload(wl, prec)
+            out, info = plan.solve(net, tol=tol)
+            gc, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+            assert st == mfs.MFS_OK
+            add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
+            plan.close()
+    return rows
+
+
+def test_parity_report():
+    rows = _rows(W.STOKES) + _rows(W.LAPLACE)
+    lines = [f"{'output':24s} {'kind':8s} {'prec':6s} {'rel_inf':>10s} {'bar':>8s}"]
+    for name, kind, prec, err, bar in rows:
+        lines.append(f"{name:24s} {kind:8s} {prec:6s} {err:10.2e} {bar:8.0e}")
+    text = "\n".join(lines)
+    print("\n" + text)
+    path = os.environ.get("MFS_PARITY_REPORT")
+    if path:
+        with open(path, "w") as f:
+            f.write(text + "\n")
+    bad = [r for r in rows if not r[3] <= r[4]]
+    assert not bad, bad
