@@ -236,6 +236,26 @@ def small_cluster(n_body: int, kind: int, n_src: int, n_trg: int, seed: int, axe
                     np.array([0, n_body], np.int64), np.array([kind], np.int32), [net])
 
 
+def with_proxy_scale(wl: Workload, scale: float) -> Workload:
+    """The same suspension with every shape's proxies regenerated on the
+    surface scaled by `scale` (same count).  For the 2-way error, which pairs
+    two formulations on distinct proxy surfaces."""
+    shapes = []
+    for sh in wl.shapes:
+        a, b, c = (float(x) for x in sh.axes)
+        assert abs(a - b) < 1e-15, "proxy regeneration supports spheroids (a, a, c)"
+        shapes.append(Shape(axes=sh.axes.copy(), src=fibonacci_spheroid(sh.src.shape[0], scale * a, scale * c),
+                            trg=sh.trg.copy()))
+    return dataclasses.replace(wl, name=f"{wl.name}@proxy{scale:.4f}", shapes=shapes)
+
+
+def resistance_proxy_scale(mobility_scale: float = PROXY_SCALE) -> float:
+    """Proxy scale of the resistance problem paired with a mobility problem
+    for the 2-way error: Delta_sep^mob = 1.05 Delta_sep^res (Section 4), with
+    Delta_sep = 1 - scale."""
+    return 1.0 - (1.0 - mobility_scale) / 1.05
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """A seeded N(0,1) vector (matvec inputs for parity tests)."""
     return np.random.default_rng(np.random.SeedSequence(9000 + seed)).standard_normal(n)

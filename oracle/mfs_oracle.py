@@ -317,9 +317,9 @@ class Problem:
             self.bodies.append(Body(c, R, X, Y, key))
             if key not in self.factors:
                 if per_body:
-                    self.factors[key] = Pinv(S_L_matrix(self.kind, X, Y, c, self.mu))
+                    self.factors[key] = Pinv(self.one_body_matrix(X, Y, c))
                 else:
-                    self.factors[key] = Pinv(S_L_matrix(self.kind, sh.trg, sh.src, np.zeros(3), self.mu))
+                    self.factors[key] = Pinv(self.one_body_matrix(sh.trg, sh.src, np.zeros(3)))
         self.per_body = per_body
         self.X = np.concatenate([b.X for b in self.bodies])
         self.Y = np.concatenate([b.Y for b in self.bodies])
@@ -327,6 +327,10 @@ class Problem:
         self.src_body = np.concatenate([np.full(b.Y.shape[0], k, np.int32) for k, b in enumerate(self.bodies)])
         self.trg_off = np.concatenate([[0], np.cumsum([self.dim * b.X.shape[0] for b in self.bodies])])
         self.src_off = np.concatenate([[0], np.cumsum([self.dim * b.Y.shape[0] for b in self.bodies])])
+
+    def one_body_matrix(self, X, Y, centre) -> np.ndarray:
+        """The block whose pseudo-inverse preconditions body k: S_L (Section 3.3)."""
+        return S_L_matrix(self.kind, X, Y, centre, self.mu)
 
     @classmethod
     def from_workload(cls, wl, sys_index: int = 0, per_body: bool = False):
@@ -379,7 +383,7 @@ class Problem:
 
     def S_L(self, k: int) -> np.ndarray:
         b = self.bodies[k]
-        return S_L_matrix(self.kind, b.X, b.Y, b.centre, self.mu)
+        return self.one_body_matrix(b.X, b.Y, b.centre)
 
     # -- pair sums over the whole suspension -------------------------------------
     def _p2p(self, strengths: np.ndarray, skip: bool, rows: Optional[np.ndarray] = None):
@@ -491,3 +495,77 @@ class Problem:
         np.add.at(grad, self.trg_body, gx)
         np.add.at(grad, self.src_body, gy)
         return float(np.sum(U * U)), -grad, dict(sol=sol, w=w, adj_iters=it_adj)
+
+
+# ---------------------------------------------------------------------------
+# The Dirichlet problems: capacitance (Section 2.1) and resistance (Section 2.2),
+# one-body preconditioned as in Section 2.4 and Algorithm 1
+# ---------------------------------------------------------------------------
+
+class ResistanceProblem(Problem):
+    """One suspension with Dirichlet data: capacitance (Laplace, given body
+    potentials phi^(k)) or resistance (Stokes, given rigid velocities U^(k)).
+
+    The square system (2sysprec): gamma^(k) + sum_{k' != k} S^(kk') S^(k'k')+ gamma^(k')
+    = eta^(k), right-preconditioned by each body's own block S^(kk) (no
+    projection, no L_r).  Data: eta^(k) = phi^(k) 1_M, or b = K_M U (Section 2.2).
+    Outputs: q^(k) = sum_j alpha_j^(k) (eq. (qkgauss)), or F = K_N^T lambda
+    (eq. (force_def))."""
+
+    def one_body_matrix(self, X, Y, centre) -> np.ndarray:
+        return S_block(self.kind, X, Y, self.mu)
+
+    def project(self, k: int, lam_k: np.ndarray) -> np.ndarray:
+        return lam_k  # no projection in this formulation
+
+    def rhs(self, data, rows=None):
+        """Dirichlet data at the collocation points: phi^(k) 1_M, or
+        v^(k) + omega^(k) x (x_i - c^(k)) (eq. (rbm)) stacked as K_M U."""
+        data = np.asarray(data, np.float64)
+        if self.kind == LAPLACE:
+            b = np.concatenate([np.full(bd.X.shape[0], data[k]) for k, bd in enumerate(self.bodies)])
+        else:
+            b = np.concatenate([K_matrix(bd.X, bd.centre) @ data[k] for k, bd in enumerate(self.bodies)])
+        if rows is not None:
+            b = b[self._row_index(rows)]
+        return b, np.zeros(self.n_lambda)
+
+    def extract(self, gamma: np.ndarray, s0=None):
+        """lambda^(k) = S^(kk)+ gamma^(k) (Algorithm 1, SOLVE); q^(k) = sum alpha^(k)
+        or F^(k) = K_N^(k)T lambda^(k)."""
+        lam = np.concatenate([self.pinv_apply(k, self.gblock(gamma, k)) for k in range(len(self.bodies))])
+        if self.kind == LAPLACE:
+            out = np.array([np.sum(self.sblock(lam, k)) for k in range(len(self.bodies))])
+        else:
+            out = np.stack([K_matrix(b.Y, b.centre).T @ self.sblock(lam, k) for k, b in enumerate(self.bodies)])
+        return out, lam, lam.copy()
+
+    def dense_matrix(self) -> np.ndarray:
+        """The square matrix of eq. (2sysprec) from dense blocks and explicitly
+        formed pseudo-inverses (tiny sizes only)."""
+        P = len(self.bodies)
+        A = np.eye(self.n_gamma)
+        for k in range(P):
+            for kp in range(P):
+                if kp != k:
+                    bk, bkp = self.bodies[k], self.bodies[kp]
+                    Pk = np.linalg.pinv(S_block(self.kind, bkp.X, bkp.Y, self.mu), rcond=0.0)
+                    A[self.trg_off[k]:self.trg_off[k + 1], self.trg_off[kp]:self.trg_off[kp + 1]] = \
+                        S_block(self.kind, bk.X, bkp.Y, self.mu) @ Pk
+        return A
+
+    def velocity_loss_gradient(self, *a, **k):
+        raise NotImplementedError("the adjoint gradient is defined for the mobility formulation")
+
+
+def two_way_error(res: "ResistanceProblem", mob: Problem, U_ref, tol: float = 1e-10) -> dict:
+    """The 2-way error (eq. (2way)): F from the resistance solve with data
+    U_ref, then U from the mobility solve with data F;
+    eps = ||U - U_ref||_inf / ||U_ref||_inf.  For Laplace the same with
+    potentials and charges.  The two problems should use distinct proxy
+    surfaces (Section 4: Delta_sep^mob = 1.05 Delta_sep^res)."""
+    U_ref = np.asarray(U_ref, np.float64)
+    r = res.solve(U_ref, tol=tol)
+    m = mob.solve(r["out"], tol=tol)
+    err = float(np.abs(m["out"] - U_ref).max() / np.abs(U_ref).max())
+    return dict(eps=err, F=r["out"], U=m["out"], iters_res=r["iters"], iters_mob=m["iters"])

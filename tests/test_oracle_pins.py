@@ -18,6 +18,11 @@ independently of the oracle's own formulas (CPU only).
 * Symmetry and positivity of the mobility matrix, translation invariance,
   rotation covariance, two-body far-field asymptotics.
 * Adjoint: dot-product identity and central finite differences of the loss.
+* Capacitance / resistance (Section 2, Algorithm 1): one sphere's drag, torque
+  and capacitance; P = 1 least squares with the net quantities of eqs.
+  (qkgauss), (force_eq); the matvec of eq. (2sysprec) assembled from dense
+  blocks; symmetry and positivity of the resistance matrix; the 2-way error
+  (eq. (2way)) small and falling with N.
 * A planted mistake in the oracle makes a pin fail.
 """
 import numpy as np
@@ -307,6 +312,103 @@ def test_velocity_loss_gradient_matches_finite_differences():
 
 
 # ---------------------------------------------------------------------------
+# Dirichlet formulations: capacitance and resistance (Section 2, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def test_resistance_single_sphere_closed_form():
+    """Stokes drag f = 6 pi mu a v and torque t = 8 pi mu a^3 omega of one
+    sphere; capacitance q = 4 pi a phi (textbook closed forms)."""
+    wl = W.single_sphere(W.STOKES)
+    U = np.random.default_rng(7).standard_normal(6)
+    F = O.ResistanceProblem.from_workload(wl).solve(U[None], tol=1e-13)["out"][0]
+    assert rel_inf(F[:3], 6 * np.pi * U[:3]) < 1e-6
+    assert rel_inf(F[3:], 8 * np.pi * U[3:]) < 1e-6
+    q = O.ResistanceProblem.from_workload(W.single_sphere(W.LAPLACE)).solve(np.array([0.5]), tol=1e-13)["out"][0]
+    assert abs(q / (4 * np.pi * 0.5) - 1.0) < 1e-7
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_resistance_single_body_is_least_squares(kind):
+    """P = 1: the preconditioned system is the identity and lambda is the
+    least-squares solution of S^(11) lambda = data (eq. (1sys), (ressyst))."""
+    wl = W.small_cluster(1, kind, 60, 130, seed=4)
+    pr = O.ResistanceProblem.from_workload(wl, per_body=True)
+    g = W.random_vector(pr.n_gamma, 6)
+    assert rel_inf(pr.matvec(g), g) < 1e-15
+    data = np.random.default_rng(8).standard_normal((1, 6) if kind == W.STOKES else 1)
+    sol = pr.solve(data, tol=1e-13)
+    X, _ = wl.world_points("trg")
+    Y, _ = wl.world_points("src")
+    c = wl.centre[0]
+    b = (np.full(X.shape[0], data[0]) if kind == W.LAPLACE else
+         (data[0][:3] + np.cross(data[0][3:], X - c)).reshape(-1))   # v + omega x (x - c), eq. (rbm)
+    assert rel_inf(sol["gamma"], b) < 1e-13
+    lam_ls = np.linalg.lstsq(O.S_block(kind, X, Y), b, rcond=None)[0]
+    assert rel_inf(sol["lam"], lam_ls) < 1e-9
+    lam_ls = lam_ls.reshape(-1, 3) if kind == W.STOKES else lam_ls
+    want = (np.sum(lam_ls) if kind == W.LAPLACE else
+            np.concatenate([lam_ls.sum(0), np.cross(Y - c, lam_ls).sum(0)]))  # eqs. (qkgauss), (force_eq)
+    assert rel_inf(sol["out"][0], want) < 1e-9
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_resistance_matvec_equals_assembled_square_system(kind):
+    """The matvec and GMRES solve equal eq. (2sysprec) assembled from dense
+    blocks and explicit per-body pseudo-inverses."""
+    wl = W.small_cluster(3, kind, 30, 70, seed=9)
+    pr = O.ResistanceProblem.from_workload(wl)
+    X, tb = wl.world_points("trg")
+    Y, sb = wl.world_points("src")
+    d = 3 if kind == W.STOKES else 1
+    P = wl.n_body
+    rows = [np.flatnonzero(np.repeat(tb == k, d)) for k in range(P)]
+    cols = [np.flatnonzero(np.repeat(sb == k, d)) for k in range(P)]
+    A = np.eye(d * X.shape[0])
+    for k in range(P):
+        for kp in range(P):
+            if k != kp:
+                Skkp = O.S_block(kind, X[tb == k], Y[sb == kp])
+                Pkp = np.linalg.pinv(O.S_block(kind, X[tb == kp], Y[sb == kp]), rcond=0.0)
+                A[np.ix_(rows[k], rows[kp])] = Skkp @ Pkp
+    g = W.random_vector(pr.n_gamma, 10)
+    assert rel_inf(pr.matvec(g), A @ g) < 1e-10
+    data = wl.net[0]
+    sol = pr.solve(data, tol=1e-13)
+    assert rel_inf(sol["gamma"], np.linalg.solve(A, sol["b"])) < 1e-10
+
+
+def test_resistance_matrix_spd_and_inverse_of_mobility():
+    """The resistance matrix R (F = R U) is symmetric positive definite and
+    the mobility matrix is its inverse (Section 1.2), here to the
+    discretisation error (R and M from 12 solves each, same proxies)."""
+    wl = W.small_cluster(2, W.STOKES, 150, 300, seed=11, axes=(1.0, 1.0, 1.0))
+    pr = O.ResistanceProblem.from_workload(wl)
+    R = np.stack([pr.solve(e.reshape(2, 6), tol=1e-13)["out"].reshape(-1) for e in np.eye(12)], axis=1)
+    assert np.abs(R - R.T).max() < 1e-3 * np.abs(R).max()
+    assert np.linalg.eigvalsh(0.5 * (R + R.T)).min() > 0
+    Mm = _mobility_matrix(O.Problem.from_workload(wl))
+    assert np.abs(R @ Mm - np.eye(12)).max() < 1e-4
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_two_way_error_small_and_converging(kind):
+    """Resistance (capacitance) then mobility (elastance) returns the input
+    data (eq. (2way)): the two formulations invert each other up to the
+    discretisation error, which falls as N grows.  Distinct proxy surfaces,
+    Delta_sep^mob = 1.05 Delta_sep^res (Section 4)."""
+    eps = []
+    for n in (60, 240):
+        wl = W.small_cluster(3, kind, n, 2 * n, seed=41, axes=(1.0, 1.0, 1.0))
+        wr = W.with_proxy_scale(wl, W.resistance_proxy_scale())
+        data = np.random.default_rng(8).standard_normal((3, 6) if kind == W.STOKES else 3)
+        r = O.two_way_error(O.ResistanceProblem.from_workload(wr), O.Problem.from_workload(wl), data, tol=1e-12)
+        eps.append(r["eps"])
+        assert r["iters_res"] >= r["iters_mob"]   # mobility needs fewer iterations (Section 4)
+    assert eps[1] < eps[0] / 5
+    assert eps[1] < (1e-4 if kind == W.STOKES else 1e-6)
+
+
+# ---------------------------------------------------------------------------
 # a mistake planted in the oracle must be caught
 # ---------------------------------------------------------------------------
 
@@ -356,3 +458,14 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(O, "p2p", p2p_double)
     phi = O.Problem.from_workload(wl_l).solve(np.ones(1), tol=1e-12)["out"][0]
     assert abs(phi * 4 * np.pi - 1.0) > 1e-2
+    monkeypatch.setattr(O, "p2p", good_p2p)
+    # (d - c) x omega instead of omega x (x - c) in the rigid-motion data: the torque pin fails
+    good_rhs = O.ResistanceProblem.rhs
+
+    def rhs_flipped(self, data, rows=None):
+        data = np.asarray(data, np.float64) * np.array([1, 1, 1, -1, -1, -1])
+        return good_rhs(self, data, rows)
+
+    monkeypatch.setattr(O.ResistanceProblem, "rhs", rhs_flipped)
+    with pytest.raises(AssertionError):
+        test_resistance_single_sphere_closed_form()
