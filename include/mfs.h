@@ -144,6 +144,18 @@ int mfs_p2p_stokes_backward(int64_t n_sys, const int64_t *sys_body_ptr, const in
  * ------------------------------------------------------------------------- */
 typedef struct mfs_plan_s *mfs_plan;
 
+/* Formulation of a plan.
+ * MFS_MOBILITY: the paper's new formulations (Section 3): elastance (Laplace,
+ *   given net charges, unknown potentials) and mobility (Stokes, given net
+ *   forces and torques, unknown rigid velocities), one-body preconditioned
+ *   with S_L^+ and the projection (I - L) (eq. (2esysprec)).
+ * MFS_RESISTANCE: the Dirichlet formulations (Section 2): capacitance
+ *   (Laplace, given potentials phi^(k), unknown charges q^(k)) and resistance
+ *   (Stokes, given rigid velocities U^(k), unknown forces and torques F^(k)),
+ *   one-body preconditioned with S^(kk)+ and no projection (eq. (2sysprec),
+ *   Algorithm 1). */
+enum { MFS_MOBILITY = 0, MFS_RESISTANCE = 1 };
+
 typedef struct {
     int32_t precision;             /* MFS_MIXED or MFS_FP64: matvec used inside GMRES */
     double mu;                     /* Stokes viscosity (> 0) */
@@ -158,11 +170,15 @@ typedef struct {
     const int32_t *shape_n_trg;    /* [host] [n_shape] M per shape (M >= N) */
     const double *shape_src;       /* [host] concatenated local proxies, sum(N) x 3 */
     const double *shape_trg;       /* [host] concatenated local collocation points, sum(M) x 3 */
+    int32_t formulation;           /* MFS_MOBILITY (0, also for a zero-initialised descriptor) or MFS_RESISTANCE */
 } mfs_plan_desc;
 
-/* Builds a plan: uploads geometry, assembles S_L for every (shape, kind) in
- * FP64 on the device, factors it (FP64 SVD), stores U^T and W = V Sigma^{-1}
- * in FP64 and FP32, and the per-body Gram inverses.  Synchronous. */
+/* Builds a plan: uploads geometry, assembles S_L (MFS_MOBILITY) or S^(kk)
+ * (MFS_RESISTANCE) for every (shape, kind) in FP64 on the device, factors it
+ * (FP64 SVD), stores U^T and W = V Sigma^{-1} in FP64 and FP32, and the
+ * per-body Gram inverses.  Synchronous.  Below, "S_L" stands for the plan's
+ * one-body block, and the projection (I - L) is the identity in a
+ * MFS_RESISTANCE plan. */
 int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *desc, void *stream);
 int mfs_plan_destroy(mfs_plan plan);
 /* Totals of the three vector layouts above, and the smallest
@@ -177,10 +193,15 @@ int mfs_plan_sizes(mfs_plan plan, int64_t *n_gamma, int64_t *n_lambda, int64_t *
  * strength0 [device] lambda layout (may be NULL).  prec selects the pair
  * arithmetic of u_0. */
 int mfs_rhs(mfs_plan plan, const double *net, double *b, double *strength0, int prec, void *stream);
+/* In a MFS_RESISTANCE plan, `net` holds the Dirichlet data per body (net
+ * layout): the potential phi^(k), or the rigid velocities [v; omega]; then
+ * b = phi^(k) 1_M, or b = K_M U, v + omega x (x_i - c) at every collocation
+ * point (eq. (rbm), Section 2.2); no pair sum runs, prec is ignored and
+ * strength0 (if given) is set to 0. */
 
 /* Per-body pseudo-inverse blocks (eq. (pseudo); Remark "congruent"):
  *   out = S_L^+ in            (in: gamma layout, out: lambda layout)
- *   flags & MFS_PROJECT:   out = (I - L) S_L^+ in
+ *   flags & MFS_PROJECT:   out = (I - L) S_L^+ in   (MFS_EINVAL in a MFS_RESISTANCE plan)
  *   flags & MFS_TRANSPOSE: out = (S_L^+)^T in   (in: lambda layout, out: gamma
  *                          layout; with PROJECT: (S_L^+)^T (I - L) in)
  * prec selects FP32 MFMA (MFS_MIXED) or FP64 MFMA (MFS_FP64) GEMMs. */
@@ -212,6 +233,9 @@ int mfs_gmres_solve(mfs_plan plan, const double *b, double *gamma, double tol, i
  * full strength (I - L) lambda + s_0 (strength0 may be NULL: taken as 0). */
 int mfs_extract(mfs_plan plan, const double *gamma, const double *strength0, double *out, double *sigma,
                 void *stream);
+/* In a MFS_RESISTANCE plan: lambda = S^(kk)+ gamma (Algorithm 1, SOLVE),
+ * out = q^(k) = sum_j alpha_j (eq. (qkgauss)) or [f; t] = K_N^T lambda
+ * (eq. (force_def)); sigma receives lambda. */
 
 /* Gradient of a loss J(out) with respect to the body centres, through the
  * whole solve (bodies move rigidly with their centres; shapes, rotations and
@@ -224,6 +248,7 @@ int mfs_extract(mfs_plan plan, const double *gamma, const double *strength0, dou
 int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strength0, const double *grad_out,
                        double *grad_centre, double tol, int32_t max_iter, int32_t max_refine,
                        int32_t *iters, double *relres, void *stream);
+/* (MFS_MOBILITY plans only; MFS_EUNSUPPORTED for MFS_RESISTANCE.) */
 
 /* Instrumentation.  With timing enabled, every pair-sum launch of the plan's
  * matvec (the dominant kernel) is bracketed by HIP events recorded on the

@@ -376,6 +376,8 @@ __global__ __launch_bounds__(256) void completion_kernel(BodyView bv, const doub
 }
 
 // Recovery: out = -mean(alpha) (Laplace) or -K_N^T lambda (Stokes); sigma = (I - L) lambda + s0.
+// Dirichlet formulations (Section 2): out = sum(alpha) = q (eq. (qkgauss)) or
+// K_N^T lambda = [f; t] (eq. (force_def)); sigma = lambda.
 __global__ __launch_bounds__(256) void extract_kernel(BodyView bv, const double *__restrict__ lam,
                                                       const double *__restrict__ s0, double *__restrict__ out,
                                                       double *__restrict__ sigma) {
@@ -385,11 +387,17 @@ __global__ __launch_bounds__(256) void extract_kernel(BodyView bv, const double 
     const int n = bv.n_src[b];
     const int64_t off = bv.lam_off[b];
     const int64_t row0 = bv.src_row[b];
+    if (bv.dirichlet && sigma)
+        for (int j = threadIdx.x; j < (kind == MFS_LAPLACE ? n : 3 * n); j += blockDim.x) sigma[off + j] = lam[off + j];
     if (kind == MFS_LAPLACE) {
         double s[1] = {0.0};
         for (int j = threadIdx.x; j < n; j += blockDim.x) s[0] += lam[off + j];
         block_sum<1>(s, reinterpret_cast<double(*)[1]>(sh));
         const double mean = s[0] / n;
+        if (bv.dirichlet) {
+            if (threadIdx.x == 0 && out) out[bv.net_off[b]] = s[0];
+            return;
+        }
         if (threadIdx.x == 0 && out) out[bv.net_off[b]] = -mean;
         if (sigma)
             for (int j = threadIdx.x; j < n; j += blockDim.x)
@@ -407,8 +415,8 @@ __global__ __launch_bounds__(256) void extract_kernel(BodyView bv, const double 
     }
     block_sum<6>(w, sh);
     if (threadIdx.x == 0 && out)
-        for (int q = 0; q < 6; ++q) out[bv.net_off[b] + q] = -w[q];
-    if (sigma) {
+        for (int q = 0; q < 6; ++q) out[bv.net_off[b] + q] = bv.dirichlet ? w[q] : -w[q];
+    if (sigma && !bv.dirichlet) {
         const double *Gi = bv.gram_inv + 36 * b;
         double z[6];
         for (int r = 0; r < 6; ++r) {
@@ -523,6 +531,7 @@ __global__ void sl_stokes_T_kernel(int M, int N, const double *__restrict__ trg,
 }
 
 // Stokes step B: SL[row, col] = S[row, col] - sum_q T[row][q] K_N[col][q]
+// (T null: the bare block S, for the Dirichlet formulations)
 __global__ void sl_stokes_fill_kernel(int M, int N, const double *__restrict__ trg, const double *__restrict__ src,
                                       const double *__restrict__ T, double mu, double *__restrict__ SL) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // target point
@@ -538,15 +547,16 @@ __global__ void sl_stokes_fill_kernel(int M, int N, const double *__restrict__ t
         const int64_t col = 3 * j + c;
         for (int a = 0; a < 3; ++a) {
             double s = G[a][c];
-            for (int q = 0; q < 6; ++q) s -= T[(3 * i + a) * 6 + q] * Kentry(y, c, q);
+            if (T)
+                for (int q = 0; q < 6; ++q) s -= T[(3 * i + a) * 6 + q] * Kentry(y, c, q);
             SL[(3 * i + a) + col * ld] = s;
         }
     }
 }
 
-// Laplace: SL[i, j] = G_ij - mean_j' G_ij' + 1/N
+// Laplace: SL[i, j] = G_ij - mean_j' G_ij' + 1/N  (plain: the bare block G_ij)
 __global__ void sl_laplace_kernel(int M, int N, const double *__restrict__ trg, const double *__restrict__ src,
-                                  double *__restrict__ SL) {
+                                  int plain, double *__restrict__ SL) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const double *x = trg + 3 * i;
@@ -560,7 +570,30 @@ __global__ void sl_laplace_kernel(int M, int N, const double *__restrict__ trg, 
     for (int j = 0; j < N; ++j) {
         const double *y = src + 3 * j;
         const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
-        SL[i + (int64_t)j * M] = 1.0 / (4.0 * PI * sqrt(d0 * d0 + d1 * d1 + d2 * d2)) - mean + 1.0 / N;
+        const double g = 1.0 / (4.0 * PI * sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+        SL[i + (int64_t)j * M] = plain ? g : g - mean + 1.0 / N;
+    }
+}
+
+// Dirichlet data at the collocation points of body b (gamma layout): the
+// potential phi^(k) at every point (Section 2.1), or the rigid-body velocity
+// v + omega x (x_i - c) (eq. (rbm); b = K_M U, Section 2.2).
+__global__ __launch_bounds__(256) void dirichlet_rhs_kernel(BodyView bv, const double *__restrict__ data,
+                                                            double *__restrict__ rhs) {
+    const int64_t b = blockIdx.x;
+    const int m = bv.n_trg[b];
+    const int64_t off = bv.gam_off[b];
+    const double *u = data + bv.net_off[b];
+    if (bv.kind[b] == MFS_LAPLACE) {
+        for (int i = threadIdx.x; i < m; i += blockDim.x) rhs[off + i] = u[0];
+        return;
+    }
+    const int64_t row0 = bv.trg_row[b];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double *d = bv.trg_off64 + 4 * (row0 + i);
+        double c[3];
+        cross3(u + 3, d, c);
+        for (int q = 0; q < 3; ++q) rhs[off + 3 * i + q] = u[q] + c[q];
     }
 }
 
@@ -657,6 +690,13 @@ int launch_extract(const BodyView &bv, const double *lam, const double *s0, doub
     return MFS_OK;
 }
 
+int launch_dirichlet_rhs(const BodyView &bv, const double *data, double *b, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    dirichlet_rhs_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, data, b);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
 int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s) {
     if (bv.n_body == 0) return MFS_OK;
     grad_lambda_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, grad_out, glam);
@@ -680,15 +720,17 @@ int launch_body_grad_reduce(int64_t n_body, const int32_t *trg_ptr, const int32_
 }
 
 int launch_assemble_SL(int kind, int M, int N, const double *trg, const double *src, const double *gram_inv6,
-                       double mu, double *SL, double *work, hipStream_t s) {
+                       double mu, bool plain, double *SL, double *work, hipStream_t s) {
     if (kind == MFS_LAPLACE) {
-        sl_laplace_kernel<<<(M + 127) / 128, 128, 0, s>>>(M, N, trg, src, SL);
+        sl_laplace_kernel<<<(M + 127) / 128, 128, 0, s>>>(M, N, trg, src, plain ? 1 : 0, SL);
         MFS_HIP_TRY(hipGetLastError());
         return MFS_OK;
     }
-    sl_stokes_T_kernel<<<(M + 63) / 64, 64, 0, s>>>(M, N, trg, src, gram_inv6, mu, work);
-    MFS_HIP_TRY(hipGetLastError());
-    sl_stokes_fill_kernel<<<dim3((M + 127) / 128, N), 128, 0, s>>>(M, N, trg, src, work, mu, SL);
+    if (!plain) {
+        sl_stokes_T_kernel<<<(M + 63) / 64, 64, 0, s>>>(M, N, trg, src, gram_inv6, mu, work);
+        MFS_HIP_TRY(hipGetLastError());
+    }
+    sl_stokes_fill_kernel<<<dim3((M + 127) / 128, N), 128, 0, s>>>(M, N, trg, src, plain ? nullptr : work, mu, SL);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -311,6 +311,7 @@ struct Factor {
 
 struct mfs_plan_s {
     int prec = MFS_MIXED;
+    int formulation = MFS_MOBILITY;
     double mu = 1.0;
     int64_t n_sys = 0, n_body = 0;
     std::vector<int64_t> sys_body_ptr;
@@ -392,6 +393,8 @@ struct mfs_plan_s {
         v.rot = d_rot.as<double>();
         v.gram_inv = d_gram_inv.as<double>();
         v.src_off64 = d_src_off64.as<double>();
+        v.trg_off64 = d_trg_off64.as<double>();
+        v.dirichlet = formulation == MFS_RESISTANCE ? 1 : 0;
         return v;
     }
 };
@@ -620,7 +623,8 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
             const int N = d->shape_n_src[F.shape], M = d->shape_n_trg[F.shape];
             const double *P = pts.as<double>() + pts_off[q];
             MFS_TRY(launch_assemble_SL(F.kind, M, N, P, P + 3 * (size_t)M, gi.as<double>() + 36 * q, p->mu,
-                                       SL.as<double>() + q * smn, work.as<double>(), s));
+                                       p->formulation == MFS_RESISTANCE, SL.as<double>() + q * smn,
+                                       work.as<double>(), s));
         }
         rocblas_status st = rocsolver_dgesvd_strided_batched(
             h, rocblas_svect_singular, rocblas_svect_singular, m, n, SL.as<double>(), m, smn, Sv.as<double>(), n,
@@ -712,6 +716,8 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     if (!out || !d) return fail(MFS_EINVAL, "NULL plan or descriptor");
     *out = nullptr;
     if (d->precision != MFS_MIXED && d->precision != MFS_FP64) return fail(MFS_EINVAL, "unknown precision");
+    if (d->formulation != MFS_MOBILITY && d->formulation != MFS_RESISTANCE)
+        return fail(MFS_EINVAL, "unknown formulation");
     if (d->n_sys < 1 || !d->sys_body_ptr || !d->sys_kind) return fail(MFS_EINVAL, "bad system description");
     if (d->sys_body_ptr[0] != 0) return fail(MFS_EINVAL, "sys_body_ptr[0] must be 0");
     for (int64_t sy = 0; sy < d->n_sys; ++sy) {
@@ -742,6 +748,7 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     std::unique_ptr<mfs_plan_s> p(new mfs_plan_s());
     p->prec = d->precision;
+    p->formulation = d->formulation;
     p->mu = d->mu;
     p->n_sys = d->n_sys;
     p->n_body = nb;
@@ -1062,7 +1069,7 @@ int harvest_timer(mfs_plan p, int prec) {
 }
 
 int matvec_impl(mfs_plan p, const double *gamma, double *out, int prec, const int32_t *sys_active, hipStream_t s) {
-    MFS_TRY(precond_fwd(p, gamma, prec, true, nullptr, prec, s));
+    MFS_TRY(precond_fwd(p, gamma, prec, p->formulation == MFS_MOBILITY, nullptr, prec, s));
     P2PLaunch L = fwd_launch(p, prec);
     L.skip_same = true;
     L.addend = gamma;
@@ -1090,8 +1097,9 @@ int matvec_adjoint_impl(mfs_plan p, const double *w, double *out, int prec, cons
     L.out = p->ws_l64c.as<double>();
     L.sys_active = sys_active;
     MFS_TRY(launch_p2p(p->p2p_tr, L, s));
-    MFS_TRY(launch_project(p->view(), p->ws_l64c.as<double>(), false, false, true, p->ws_l64c.as<double>(), nullptr,
-                           nullptr, 0, s));
+    if (p->formulation == MFS_MOBILITY)
+        MFS_TRY(launch_project(p->view(), p->ws_l64c.as<double>(), false, false, true, p->ws_l64c.as<double>(),
+                               nullptr, nullptr, 0, s));
     MFS_TRY(precond_tr(p, p->ws_l64c.as<double>(), prec, false, out, s));
     return launch_add_inplace(p->n_gamma, w, out, s);
 }
@@ -1109,6 +1117,10 @@ int mfs_rhs(mfs_plan p, const double *net, double *b, double *strength0, int pre
     MFS_TRY(check_plan_prec(p, prec));
     if (!net || !b) return fail(MFS_EINVAL, "NULL net or b");
     hipStream_t s = (hipStream_t)stream;
+    if (p->formulation == MFS_RESISTANCE) {
+        if (strength0) MFS_TRY(launch_fill(p->n_lambda, 0.0, strength0, s));
+        return launch_dirichlet_rhs(p->view(), net, b, s);
+    }
     MFS_TRY(launch_completion(p->view(), net, strength0, prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr,
                               prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr, prec, s));
     P2PLaunch Lr = fwd_launch(p, prec);
@@ -1122,6 +1134,8 @@ int mfs_precond_apply(mfs_plan p, const double *in, double *out, int flags, int 
     MFS_TRY(check_plan_prec(p, prec));
     if (!in || !out) return fail(MFS_EINVAL, "NULL in or out");
     if (flags & ~(MFS_PROJECT | MFS_TRANSPOSE)) return fail(MFS_EINVAL, "unknown flags");
+    if ((flags & MFS_PROJECT) && p->formulation == MFS_RESISTANCE)
+        return fail(MFS_EINVAL, "no projection in the resistance formulation");
     hipStream_t s = (hipStream_t)stream;
     if (flags & MFS_TRANSPOSE) return precond_tr(p, in, prec, (flags & MFS_PROJECT) != 0, out, s);
     return precond_fwd(p, in, prec, (flags & MFS_PROJECT) != 0, out, -1, s);
@@ -1433,6 +1447,8 @@ extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double 
                                   double *grad_centre, double tol, int32_t max_iter, int32_t max_refine, int32_t *iters,
                                   double *relres, void *stream) {
     if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (p->formulation != MFS_MOBILITY)
+        return fail(MFS_EUNSUPPORTED, "centre gradients are defined for the mobility / elastance formulation");
     if (!gamma || !grad_out || !grad_centre) return fail(MFS_EINVAL, "NULL gamma, grad_out or grad_centre");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFS_EINVAL, "tol must be finite and > 0");
     if (max_iter < 1 || max_iter > 2000) return fail(MFS_EINVAL, "max_iter must be in [1, 2000]");

@@ -186,6 +186,8 @@ struct BodyView {
     const double *rot;         // [n_body][9]
     const double *gram_inv;    // [n_body][36] (Stokes bodies)
     const double *src_off64;   // [n_src][4] world-axis offsets of the proxies
+    const double *trg_off64;   // [n_trg][4] world-axis offsets of the collocation points
+    int dirichlet;             // 1: capacitance / resistance formulation (no projection)
 };
 
 // in (world frame fp64) -> out (shape frame, float or double); gamma layout (M points per body)
@@ -202,6 +204,8 @@ int launch_completion(const BodyView &bv, const double *net, double *s0, void *s
                       hipStream_t s);
 int launch_extract(const BodyView &bv, const double *lam, const double *s0, double *out, double *sigma,
                    hipStream_t s);
+// Dirichlet data at the collocation points: phi 1_M or v + omega x (x - c) (gamma layout)
+int launch_dirichlet_rhs(const BodyView &bv, const double *data, double *b, hipStream_t s);
 int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s);
 int launch_set_src_strength(const BodyView &bv, const double *str, void *srcS, void *srcL, int prec, hipStream_t s);
 int launch_body_grad_reduce(int64_t n_body, const int32_t *trg_ptr, const int32_t *src_ptr, const double *gt,
@@ -210,8 +214,9 @@ int launch_make_factor(int rows, int cols, const double *src, int64_t ld, bool t
                        const double *cs, double *d64, float *d32, hipStream_t s);
 
 // setup
+// S_L (column-major M x N blocks of dim) or, with plain, the bare block S^(kk)
 int launch_assemble_SL(int kind, int M, int N, const double *trg, const double *src, const double *gram_inv6,
-                       double mu, double *SL, double *work, hipStream_t s);
+                       double mu, bool plain, double *SL, double *work, hipStream_t s);
 int launch_scale_rows_to_f32(int rows, int cols, const double *src, int64_t ld_src, const double *row_scale,
                              const double *col_scale, double *dst64, float *dst32, hipStream_t s);
 

@@ -21,6 +21,7 @@ MFS_EINVAL, MFS_EHIP, MFS_ENOMEM, MFS_ENUMERIC, MFS_EUNSUPPORTED = -1, -2, -3, -
 LAPLACE, STOKES = 0, 1
 FP64, MIXED = 0, 1
 SKIP_SAME_BODY, ACCUMULATE, PROJECT, TRANSPOSE = 1, 2, 4, 8
+MOBILITY, RESISTANCE = 0, 1
 
 _lib = None
 
@@ -41,7 +42,7 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("mu", ctypes.c_double), ("n_sys", ctypes.c_int64),
         ("sys_body_ptr", _i64p), ("sys_kind", _i32p), ("centre", _dp), ("rot", _dp),
         ("shape_of_body", _i32p), ("n_shape", ctypes.c_int64), ("shape_n_src", _i32p),
-        ("shape_n_trg", _i32p), ("shape_src", _dp), ("shape_trg", _dp),
+        ("shape_n_trg", _i32p), ("shape_src", _dp), ("shape_trg", _dp), ("formulation", ctypes.c_int32),
     ]
 
 
@@ -184,10 +185,11 @@ class Plan:
     """A resident solve plan (see mfs_plan_create in mfs.h)."""
 
     def __init__(self, precision: int, sys_body_ptr, sys_kind, centre, rot, shape_of_body, shape_src: Sequence,
-                 shape_trg: Sequence, mu: float = 1.0, device="cuda", stream=None):
+                 shape_trg: Sequence, mu: float = 1.0, device="cuda", stream=None, formulation: int = MOBILITY):
         self.device = torch.device(device)
         self._h = ctypes.c_void_p()
         self.precision = int(precision)
+        self.formulation = int(formulation)
         self.sys_body_ptr = _host_i64(sys_body_ptr)
         self.sys_kind = np.ascontiguousarray(np.asarray(sys_kind, dtype=np.int32))
         self.centre = np.ascontiguousarray(np.asarray(centre, dtype=np.float64))
@@ -211,6 +213,7 @@ class Plan:
         d.shape_n_trg = self.shape_n_trg.ctypes.data_as(_i32p)
         d.shape_src = self.shape_src.ctypes.data_as(_dp)
         d.shape_trg = self.shape_trg.ctypes.data_as(_dp)
+        d.formulation = self.formulation
         with torch.cuda.device(self.device):
             _check(lib().mfs_plan_create(ctypes.byref(self._h), ctypes.byref(d), _stream(stream)), "mfs_plan_create")
         ng, nl, nn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -221,9 +224,11 @@ class Plan:
         self.min_sigma_ratio = ratio.value
 
     @classmethod
-    def from_workload(cls, wl, precision: int = MIXED, device="cuda", stream=None) -> "Plan":
+    def from_workload(cls, wl, precision: int = MIXED, device="cuda", stream=None,
+                      formulation: int = MOBILITY) -> "Plan":
         return cls(precision, wl.sys_body_ptr, wl.sys_kind, wl.centre, wl.rot, wl.shape_of_body,
-                   [s.src for s in wl.shapes], [s.trg for s in wl.shapes], mu=wl.mu, device=device, stream=stream)
+                   [s.src for s in wl.shapes], [s.trg for s in wl.shapes], mu=wl.mu, device=device, stream=stream,
+                   formulation=formulation)
 
     def close(self):
         if self._h:
@@ -240,7 +245,9 @@ class Plan:
         return torch.empty(n, dtype=torch.float64, device=self.device)
 
     def rhs(self, net: torch.Tensor, prec: Optional[int] = None, stream=None):
-        """b = -u_0 and the completion strengths s_0."""
+        """b = -u_0 and the completion strengths s_0 (MOBILITY); the Dirichlet
+        data at the collocation points and s_0 = 0 (RESISTANCE; `net` holds the
+        body potentials or rigid velocities)."""
         b, s0 = self._new(self.n_gamma), self._new(self.n_lambda)
         _check(lib().mfs_rhs(self._h, _ptr(net), _ptr(b), _ptr(s0), self.precision if prec is None else prec,
                              _stream(stream)), "mfs_rhs")
