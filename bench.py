@@ -36,7 +36,10 @@ if ROOT not in sys.path:
 
 FLOPS_PER_PAIR = {1: 28.0, 0: 11.0}      # Stokes, Laplace (FMA = 2, rsqrt = 1)
 PEAK_FP32_TFLOPS = 157.3                  # MI355X FP32 vector peak (published)
-WORKLOADS = ("ellipsoids_100", "ellipsoids_1000", "batched_64", "spheres_200_grad")
+WORKLOADS = ("ellipsoids_100", "ellipsoids_1000", "batched_64", "spheres_200_grad", "ellipsoids_100_2way",
+             "ellipsoids_10000")
+# minutes-long solves: one step, no warm-up, no autotuning, no separate FP64 solve, progress lines
+LARGE = ("ellipsoids_10000",)
 
 
 def _workload(name: str, kind: int):
@@ -49,6 +52,10 @@ def _workload(name: str, kind: int):
         return W.batched_64()
     if name == "spheres_200_grad":
         return W.spheres_200()
+    if name == "ellipsoids_100_2way":
+        return W.ellipsoids_100(1)
+    if name == "ellipsoids_10000":
+        return W.ellipsoids_10000(kind)
     raise SystemExit(f"unknown workload {name}; choose from {WORKLOADS}")
 
 
@@ -152,6 +159,88 @@ def cpu_baseline(wl, budget_s: float = 15.0):
                 sample=sample + "; off-body pairs per second of that work", seconds=dt)
 
 
+def two_way_bench(args, mfs, torch, np):
+    """The 2-way test (eq. (2way)) on ellipsoids_100 (Stokes): a step is one
+    resistance solve (seeded rigid velocities U_ref -> forces F, proxies at the
+    resistance scale) followed by one mobility solve (F -> U, proxies at 0.7).
+    Reports eps_2way = |U - U_ref|_inf / |U_ref|_inf in both precisions."""
+    import mfs_workloads as W
+    wl = W.ellipsoids_100(W.STOKES)
+    wr = W.with_proxy_scale(wl, W.resistance_proxy_scale())
+    U_ref = np.random.default_rng(np.random.SeedSequence(7100)).standard_normal((wl.n_body, 6))
+    u_ref = torch.tensor(U_ref.reshape(-1), dtype=torch.float64, device="cuda")
+    off = float(sum(wl.shapes[0].trg.shape[0] for _ in range(wl.n_body)) * (wl.n_body - 1) * wl.shapes[0].src.shape[0])
+    plans = {}
+    for prec in (mfs.MIXED, mfs.FP64):
+        res = mfs.Plan.from_workload(wr, prec, formulation=mfs.RESISTANCE)
+        mob = mfs.Plan.from_workload(wl, prec)
+        if not args.no_autotune:
+            res.autotune(prec, reps=2)
+            mob.autotune(prec, reps=2)
+        plans[prec] = (res, mob)
+
+    def step(prec):
+        res, mob = plans[prec]
+        F, ir = res.solve(u_ref, tol=args.tol)
+        rmx, r64 = res.last_solve()
+        U, im = mob.solve(F, tol=args.tol)
+        mmx, m64 = mob.last_solve()
+        mv = int(rmx[0] + r64[0] + mmx[0] + m64[0])
+        pairs = mv * off + wl.n_body * wl.shapes[0].trg.shape[0] * wl.n_body * wl.shapes[0].src.shape[0]
+        eps = float((U - u_ref).abs().max() / u_ref.abs().max())
+        return eps, pairs, (int(ir["iters"][0]), int(im["iters"][0])), (int(rmx[0]), int(mmx[0]))
+
+    out = {}
+    for prec, steps in ((mfs.MIXED, args.steps), (mfs.FP64, args.fp64_steps)):
+        for _ in range(args.warmup):
+            step(prec)
+        res, mob = plans[prec]
+        if prec == mfs.MIXED:
+            for p in (res, mob):
+                p.set_timing(True)
+                p.timing(mfs.MIXED, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot = 0.0
+        for _ in range(steps):
+            eps, pairs, its, mx = step(prec)
+            tot += pairs
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[prec] = dict(step_s=dt, eps=eps, pairs=tot / steps, iters=its, mixed_mv=mx)
+        if prec == mfs.MIXED:
+            n1, ms1, _ = res.timing(mfs.MIXED)
+            n2, ms2, _ = mob.timing(mfs.MIXED)
+            for p in (res, mob):
+                p.set_timing(False)
+            out["avg_ms"] = (ms1 + ms2) / max(n1 + n2, 1)
+            out["launches"] = n1 + n2
+    mx, f64 = out[mfs.MIXED], out[mfs.FP64]
+    achieved = FLOPS_PER_PAIR[1] * off / (out["avg_ms"] * 1e-3) / 1e12
+    rec = {
+        "metric": "P2P Ginteractions/s + GMRES-to-1e-5 solve time, mixed vs FP64, 1 GPU",
+        "value": round(mx["pairs"] / mx["step_s"] / 1e9, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(mx["step_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 pairs + f64",
+        "data": "synthetic (seeded prolate spheroids; no dataset)",
+        "config": {"workload": "ellipsoids_100_2way", "bodies": wl.n_body, "proxies_per_body": 400,
+                   "collocation_per_body": 800, "kernel": "stokes resistance then mobility",
+                   "gmres_tol": args.tol, "resistance_proxy_scale": round(W.resistance_proxy_scale(), 6),
+                   "mobility_proxy_scale": 0.7},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "p2p_mixed_kernel (matvec pair sum)", "avg_launch_ms": round(out["avg_ms"], 4),
+                     "launches": out["launches"]},
+        "eps_2way_mixed": mx["eps"], "eps_2way_fp64": f64["eps"],
+        "iters_resistance_mobility_mixed": mx["iters"], "iters_resistance_mobility_fp64": f64["iters"],
+        "step_time_fp64_s": round(f64["step_s"], 5), "speedup_mixed_vs_fp64": round(f64["step_s"] / mx["step_s"], 3),
+    }
+    print(json.dumps(rec))
+    return 0
+
+
 # (targets per lane, work items, persistent grid): the autotuner's candidates
 LAUNCH_SHAPES = [(tpl, items, per) for per in (0, 1) for tpl in (1, 2) for items in (1024, 2048, 4096, 8192, 16384)]
 
@@ -179,13 +268,14 @@ def counter_sweep(plan, mfs, torch, np):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 5; 1 for the 10^4 case)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; 0 for the 10^4 case)")
     ap.add_argument("--workload", default="ellipsoids_100", choices=WORKLOADS)
     ap.add_argument("--kind", default="stokes", choices=("stokes", "laplace"),
                     help="PDE of the ellipsoid workloads (batched_64 mixes both; spheres_200_grad is Stokes)")
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="FP64 solves timed for the speedup (default 2; 0 for the 10^4 case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pair-sum launch shape")
     ap.add_argument("--counter-sweep", action="store_true",
@@ -196,6 +286,13 @@ def main():
                     help="fix the pair-sum launch shape instead of autotuning: TPL,WORK_ITEMS,PERSISTENT "
                          "(e.g. 1,16384,0; used for counter runs, which must repeat one shape)")
     args = ap.parse_args()
+    large = args.workload in LARGE
+    args.steps = args.steps if args.steps is not None else (1 if large else 5)
+    args.warmup = args.warmup if args.warmup is not None else (0 if large else 1)
+    args.fp64_steps = args.fp64_steps if args.fp64_steps is not None else (0 if large else 2)
+    if large:
+        args.no_cpu = True
+        args.no_autotune = True
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is not built)", file=sys.stderr)
@@ -207,6 +304,8 @@ def main():
     from paper_2409_04215_amd import mfs
 
     torch.cuda.set_device(0)
+    if args.workload == "ellipsoids_100_2way":
+        return two_way_bench(args, mfs, torch, np)
     kind = 0 if args.kind == "laplace" else 1
     grad = args.workload == "spheres_200_grad"
     wl = _workload(args.workload, kind)
@@ -219,20 +318,31 @@ def main():
     setup_s = time.perf_counter() - t0
     if args.counter_sweep:
         return counter_sweep(plan_mx, mfs, torch, np)
-    plan_64 = mfs.Plan.from_workload(wl, mfs.FP64)
+    plan_64 = mfs.Plan.from_workload(wl, mfs.FP64) if args.fp64_steps > 0 else None
+    max_iter = 100 if large else 200
+    if large:
+        t_start = time.perf_counter()
+
+        def report(mv, active, relres):
+            print(f"[solve] matvec {mv}: max relative residual estimate {relres:.3e}, "
+                  f"{time.perf_counter() - t_start:.0f} s", file=sys.stderr, flush=True)
+
+        plan_mx.set_progress(report)
 
     tuned = None
     if args.launch:
         tpl, items, per = (int(v) for v in args.launch.split(","))
         for p in (plan_mx, plan_64):
-            p.set_launch(tpl, items, bool(per))
+            if p is not None:
+                p.set_launch(tpl, items, bool(per))
         tuned = (-tpl if per else tpl, items, float("nan"))
     elif not args.no_autotune:
         tuned = plan_mx.autotune(mfs.MIXED, reps=3)
-        plan_64.autotune(mfs.FP64, reps=2)
+        if plan_64 is not None:
+            plan_64.autotune(mfs.FP64, reps=2)
 
     def step(plan):
-        out, info = plan.solve(net, tol=args.tol)
+        out, info = plan.solve(net, tol=args.tol, max_iter=max_iter)
         mx, f64 = plan.last_solve()
         pairs = sum((m + f) * off + rhs for (k, off, rhs), m, f in zip(per_sys, mx, f64))
         flops_mx = sum(m * off * FLOPS_PER_PAIR[k] for (k, off, rhs), m in zip(per_sys, mx))
@@ -262,21 +372,39 @@ def main():
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / args.steps
     n_mx, ms_mx, ppl = plan_mx.timing(mfs.MIXED)
-    n_chk, _, _ = plan_mx.timing(mfs.FP64)
+    n_chk, ms_chk, _ = plan_mx.timing(mfs.FP64)
     plan_mx.set_timing(False)
     value = tot_pairs / args.steps / step_s / 1e9
 
-    plan_64.solve(net, tol=args.tol)
-    plan_64.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.fp64_steps):
-        out_64, info_64, _, _, _, _ = step(plan_64)
-    torch.cuda.synchronize()
-    fp64_s = (time.perf_counter() - t0) / args.fp64_steps
-    n64, ms64, _ = plan_64.timing(mfs.FP64)
-    plan_64.set_timing(False)
-    diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
+    fp64_s = diff = None
+    info_64 = None
+    n64, ms64 = n_chk, ms_chk  # FP64 pair rate from the true-residual checks unless FP64 solves run
+    if plan_64 is not None:
+        plan_64.solve(net, tol=args.tol, max_iter=max_iter)
+        plan_64.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            out_64, info_64, _, _, _, _ = step(plan_64)
+        torch.cuda.synchronize()
+        fp64_s = (time.perf_counter() - t0) / args.fp64_steps
+        n64, ms64, _ = plan_64.timing(mfs.FP64)
+        plan_64.set_timing(False)
+        diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
+    extra = {}
+    if large and kind == 1:
+        # exact net force and torque of the strengths (eq. (force_syst)): a property of the solve
+        _, sigma = plan_mx.extract(info_mx["gamma"], info_mx["s0"], want_sigma=True)
+        Y, sb = wl.world_points("src")
+        sg = sigma.cpu().numpy().reshape(-1, 3)
+        F = np.zeros((wl.n_body, 3))
+        T = np.zeros((wl.n_body, 3))
+        np.add.at(F, sb, sg)
+        np.add.at(T, sb, np.cross(Y - wl.centre[sb], sg))
+        want = wl.net[0]
+        extra["net_force_torque_mismatch"] = float(np.abs(np.concatenate([F, T], 1) - want).max() / np.abs(want).max())
+        extra["context"] = ("the paper solves 10^4 Type T ellipsoids (delta 0.2, N_v 34) on one CPU workstation "
+                            "with an FMM in under two hours")
 
     shape = (abs(tuned[0]), tuned[1], int(tuned[0] < 0)) if tuned else (1, 2048, 0)
     traffic = (_counter_traffic(args.workload, shape)
@@ -314,19 +442,20 @@ def main():
                      "launches": n_mx, "flops_per_pair": round(flops_per_pair, 3),
                      "flops_per_launch": tot_flops / max(n_mx, 1)},
         "solve_time_mixed_s": round(step_s, 5),
-        "solve_time_fp64_s": round(fp64_s, 5),
-        "speedup_mixed_vs_fp64": round(fp64_s / step_s, 3),
+        "solve_time_fp64_s": round(fp64_s, 5) if fp64_s else None,
+        "speedup_mixed_vs_fp64": round(fp64_s / step_s, 3) if fp64_s else None,
         "matvecs_per_step_mixed": (n_mx + n_chk) / args.steps,
         "fp64_check_matvecs_per_step": n_chk / args.steps,
         "iters_per_system_last_step": [int(x) for x in np.asarray(its).reshape(-1)][:128],
         "relres_mixed_true_fp64_max": float(np.max(info_mx["relres"])),
-        "relres_fp64_max": float(np.max(info_64["relres"])),
+        "relres_fp64_max": float(np.max(info_64["relres"])) if info_64 else None,
         "p2p_kernel_ginter_s_mixed": round(ppl * n_mx / (ms_mx * 1e-3) / 1e9, 2) if ms_mx > 0 and wl.n_sys == 1 else None,
         "p2p_kernel_ginter_s_fp64": round(ppl * n64 / (ms64 * 1e-3) / 1e9, 2) if ms64 > 0 and wl.n_sys == 1 else None,
         "rel_diff_out_mixed_vs_fp64_gpu": diff,
         "setup_s": round(setup_s, 3),
         "autotuned_launch": {"targets_per_lane": abs(tuned[0]), "work_items": tuned[1],
                              "persistent_grid": tuned[0] < 0} if tuned else None,
+        **extra,
     }
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl.system(0) if wl.n_sys > 1 else wl)

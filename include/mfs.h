@@ -273,6 +273,15 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * transposed sums, and reports it ([host] outputs, may be NULL; *best_tpl is
  * negative for the persistent grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
+/* Progress of long solves.  With a callback set, mfs_gmres_solve (and the
+ * adjoint solve of mfs_solve_backward) calls it on the calling host thread
+ * after every GMRES iteration with: the matvecs spent so far (largest over
+ * systems), the number of systems still iterating, and the largest relative
+ * residual estimate among the systems of the current attempt.  A non-zero
+ * return stops the solve early; it then returns MFS_NOT_CONVERGED with the
+ * current iterates.  fn == NULL removes the callback. */
+typedef int (*mfs_progress_fn)(void *user, int32_t matvecs, int32_t active_systems, double max_relres);
+int mfs_plan_set_progress(mfs_plan plan, mfs_progress_fn fn, void *user);
 /* Fixes the launch shape of the plan's pair sums (the choices the autotuner
  * ranges over): targets_per_lane 1 or 2, work_items >= 1 (target blocks x
  * source splits, at least this many), persistent != 0 for the work-queue grid.

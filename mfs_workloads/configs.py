@@ -37,7 +37,8 @@ from typing import List
 
 import numpy as np
 
-from .geometry import fibonacci_sphere, fibonacci_spheroid, random_cluster
+from .geometry import (ellipsoid_ring_grid, fibonacci_sphere, fibonacci_spheroid, grown_sphere_cluster,
+                       random_cluster, random_rotation, ring_grid_size, shift_inward)
 
 LAPLACE = 0
 STOKES = 1
@@ -234,6 +235,47 @@ def small_cluster(n_body: int, kind: int, n_src: int, n_trg: int, seed: int, axe
     net = rr.standard_normal((n_body, 6)) if kind == STOKES else rr.standard_normal(n_body)
     return Workload(f"small_{n_body}_{kind}_{seed}", [shape], cen, rot, np.zeros(n_body, np.int32),
                     np.array([0, n_body], np.int64), np.array([kind], np.int32), [net])
+
+
+TYPE_T_AXES = (0.4, 0.6, 1.0)
+DELTA_SEP_MOBILITY = 1.05 * 0.125
+
+
+def type_t_shape(n_v: int = 34, delta_sep: float = DELTA_SEP_MOBILITY) -> Shape:
+    """The paper's Type T triaxial ellipsoid (semi-axes 0.4, 0.6, 1) on its
+    ring grid (Section 4.2): proxies on the n_v-ring grid moved inward by
+    delta_sep along the normal; collocation points on the grid with 1.15 n_v
+    Gauss-Legendre rings.  n_v = 34 gives N = 658, M = 842."""
+    axes = np.array(TYPE_T_AXES, dtype=np.float64)
+    trg = ellipsoid_ring_grid(*TYPE_T_AXES, int(round(1.15 * n_v)), n_total=ring_grid_size(1.15 * n_v))
+    src = shift_inward(ellipsoid_ring_grid(*TYPE_T_AXES, n_v), axes, delta_sep)
+    return Shape(axes=axes, src=src, trg=trg)
+
+
+def _type_t_cluster(rg, rr, n_body: int, kind: int, delta: float, n_v: int, name: str) -> Workload:
+    cen = grown_sphere_cluster(rg, n_body, delta)
+    rot = np.stack([random_rotation(rg) for _ in range(n_body)])
+    net = rr.standard_normal((n_body, 6)) if kind == STOKES else rr.standard_normal(n_body)
+    return Workload(name, [type_t_shape(n_v)], cen, rot, np.zeros(n_body, np.int32),
+                    np.array([0, n_body], np.int64), np.array([kind], np.int32), [net])
+
+
+def ellipsoids_10000(kind: int = STOKES) -> Workload:
+    """The paper's large demonstration (Section 4.2): 10^4 Type T ellipsoids,
+    each inside one sphere of a grown unit-sphere cluster whose spheres are
+    delta = 0.2 from at least one neighbour, orientations uniform on SO(3);
+    N = 658, M = 842 (n_v = 34); forces and torques (or charges) N(0,1)."""
+    def make():
+        rg, rr = _rngs(5)
+        return _type_t_cluster(rg, rr, 10000, kind, 0.2, 34, "ellipsoids_10000")
+    return _cached(f"ellipsoids_10000_k{kind}", make)
+
+
+def type_t_cluster(n_body: int, kind: int, seed: int, delta: float = 0.2, n_v: int = 34) -> Workload:
+    """A smaller cluster built like ellipsoids_10000 (for parity tests)."""
+    g, r = np.random.SeedSequence(5000 + seed).spawn(2)
+    return _type_t_cluster(np.random.default_rng(g), np.random.default_rng(r), n_body, kind, delta, n_v,
+                           f"type_t_{n_body}_{kind}_{seed}")
 
 
 def with_proxy_scale(wl: Workload, scale: float) -> Workload:

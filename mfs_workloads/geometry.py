@@ -170,3 +170,102 @@ def random_cluster(rng: np.random.Generator, n_body: int, axes, box: float, gap:
         grid.setdefault(key, []).append(k)
         k += 1
     return cen, rot
+
+
+# ---------------------------------------------------------------------------
+# The paper's large-cluster geometry (Section 4.2)
+# ---------------------------------------------------------------------------
+
+def _ellipse_perimeter(p: float, q: float) -> float:
+    """Perimeter of the ellipse with semi-axes p, q (Ramanujan's second formula)."""
+    if p + q == 0.0:
+        return 0.0
+    h = ((p - q) / (p + q)) ** 2
+    return math.pi * (p + q) * (1.0 + 3.0 * h / (10.0 + math.sqrt(4.0 - 3.0 * h)))
+
+
+def ring_grid_size(n_v: float) -> int:
+    """The paper's node count of its ellipsoid grid, 17 + 3.9 n_v + 0.44 n_v^2 (Section 4.2)."""
+    return int(round(17.0 + 3.9 * n_v + 0.44 * n_v * n_v))
+
+
+def ellipsoid_ring_grid(a: float, b: float, c: float, n_v: int, n_total: int = 0) -> np.ndarray:
+    """Quasi-uniform grid on the ellipsoid x^2/a^2 + y^2/b^2 + z^2/c^2 = 1 as the
+    paper describes it (Section 4.2): parameterise the surface by
+    (a sqrt(1-t^2) cos s, b sqrt(1-t^2) sin s, c t), take n_v Gauss-Legendre
+    nodes in t and, on each ring, equispaced (trapezoidal) nodes in s whose
+    count is proportional to the ring's perimeter (at least 3).  The
+    proportionality constant is chosen so the total is as close as possible to
+    n_total (default: the paper's count for n_v, ring_grid_size).  Consecutive
+    rings are rotated by half a step.  Returns (n, 3)."""
+    t, _ = np.polynomial.legendre.leggauss(n_v)
+    rho = np.sqrt(1.0 - t * t)
+    per = np.array([_ellipse_perimeter(a * r, b * r) for r in rho])
+    target = n_total or ring_grid_size(n_v)
+
+    def counts_for(k):
+        return np.maximum(3, np.rint(k * per / per.max()).astype(int))
+
+    lo, hi = 1.0, 4.0 * n_v
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if counts_for(mid).sum() < target:
+            lo = mid
+        else:
+            hi = mid
+    counts = min((counts_for(lo), counts_for(hi)), key=lambda q: abs(int(q.sum()) - target))
+    pts = []
+    for i, (ti, ri, ni) in enumerate(zip(t, rho, counts)):
+        s = 2.0 * math.pi * (np.arange(ni) + 0.5 * (i % 2)) / ni
+        pts.append(np.stack([a * ri * np.cos(s), b * ri * np.sin(s), np.full(ni, c * ti)], axis=1))
+    return np.concatenate(pts)
+
+
+def shift_inward(points: np.ndarray, axes, delta: float) -> np.ndarray:
+    """Points on the ellipsoid surface moved a distance delta along the inward
+    unit normal (the paper's normal-shifted proxy surface, Section 4.2)."""
+    axes = np.asarray(axes, np.float64)
+    n = points / (axes * axes)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return points - delta * n
+
+
+def grown_sphere_cluster(rng: np.random.Generator, n: int, delta: float, radius: float = 1.0,
+                         max_tries: int = 50_000_000) -> np.ndarray:
+    """Centres of n spheres of the given radius, each exactly delta (surface
+    gap) from at least one sphere placed before it and at least delta from all
+    others: every new sphere is put at distance 2 radius + delta from a
+    uniformly chosen earlier sphere in a uniform random direction, and kept if
+    it clears all others (cell-list check).  The paper grows its 10^4-ellipsoid
+    cluster from such a sphere cluster (Section 4.2)."""
+    d = 2.0 * radius + delta
+    cen = np.zeros((n, 3))
+    grid: dict = {(0, 0, 0): [0]}
+    k, tries = 1, 0
+    while k < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("grown_sphere_cluster: could not place all spheres")
+        u = rng.standard_normal(3)
+        c = cen[rng.integers(k)] + d * u / np.linalg.norm(u)
+        key = tuple(np.floor(c / d).astype(int))
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for j in grid.get((key[0] + dx, key[1] + dy, key[2] + dz), ()):
+                        if np.sum((cen[j] - c) ** 2) < d * d * (1.0 - 1e-12):
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if not ok:
+            continue
+        cen[k] = c
+        grid.setdefault(key, []).append(k)
+        k += 1
+    return cen

@@ -367,6 +367,11 @@ struct mfs_plan_s {
     bool tuned_persistent = false;
     // matvecs per system of the last GMRES solve, by precision
     std::vector<int32_t> last_mixed, last_fp64;
+    // progress callback of long solves
+    mfs_progress_fn progress = nullptr;
+    void *progress_user = nullptr;
+    bool stop_requested = false;
+    std::vector<double> prog_bnorm;  // ||b|| per system of the running solve
 
     ~mfs_plan_s() {
         for (auto &t : timer)
@@ -1328,6 +1333,21 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
             if (est[sy] <= target[sy] || hn == 0.0) live[sy] = 0;
             else scale[sy] = 1.0 / hn;
         }
+        if (p->progress) {
+            int n_live = 0, done = 0;
+            double worst = 0.0;
+            for (int sy = 0; sy < S; ++sy) {
+                done = std::max(done, counts[sy]);
+                if (!act[sy]) continue;
+                n_live += live[sy];
+                const double bn = sy < (int)p->prog_bnorm.size() && p->prog_bnorm[sy] > 0 ? p->prog_bnorm[sy] : 1.0;
+                worst = std::max(worst, est[sy] / bn);
+            }
+            if (p->progress(p->progress_user, done, n_live, worst) != 0) {
+                p->stop_requested = true;
+                std::fill(live.begin(), live.end(), 0);
+            }
+        }
         if (j + 1 < max_iter) {
             MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
             MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, p->nrm.as<double>(), 1, V + (int64_t)(j + 1) * n, s));
@@ -1365,6 +1385,8 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
         if (!std::isfinite(bn[sy])) return fail(MFS_ENUMERIC, "non-finite right-hand side");
     std::vector<double> target(S), est(S), rn(S);
     std::vector<int> counts(S, 0), active(S, 1), checks(S, 0);
+    p->prog_bnorm = bn;
+    p->stop_requested = false;
     MFS_TRY(launch_fill(n, 0.0, x, s));
     double *r = p->R.as<double>();
     MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1403,7 +1425,7 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
                 if (tn[sy] <= tol * bn[sy]) active[sy] = 0;
                 else all = false;
             }
-            if (all) break;
+            if (all || p->stop_requested) break;
             // restart from x on the true residual: solve A dx = r
             for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
             // gmres_attempt adds into x directly
@@ -1443,6 +1465,13 @@ int mfs_gmres_solve(mfs_plan p, const double *b, double *gamma, double tol, int3
 // ---------------------------------------------------------------------------
 // gradient of J(out) with respect to the centres
 // ---------------------------------------------------------------------------
+extern "C" int mfs_plan_set_progress(mfs_plan p, mfs_progress_fn fn, void *user) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    p->progress = fn;
+    p->progress_user = user;
+    return MFS_OK;
+}
+
 extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double *strength0, const double *grad_out,
                                   double *grad_centre, double tol, int32_t max_iter, int32_t max_refine, int32_t *iters,
                                   double *relres, void *stream) {

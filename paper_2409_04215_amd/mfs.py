@@ -31,6 +31,9 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
 
 
+_PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double)
+
+
 class MfsError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: status {status}: {msg}")
@@ -77,6 +80,7 @@ def lib():
         L.mfs_plan_set_graph.argtypes = [_vp, ctypes.c_int32]
         L.mfs_plan_last_solve.argtypes = [_vp, _i32p, _i32p]
         L.mfs_plan_set_launch.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]
+        L.mfs_plan_set_progress.argtypes = [_vp, _PROGRESS_FN, _vp]
         L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
@@ -320,6 +324,21 @@ class Plan:
         """Fix the pair-sum launch shape (see mfs_plan_set_launch)."""
         _check(lib().mfs_plan_set_launch(self._h, int(targets_per_lane), int(work_items), int(persistent),
                                          _stream(stream)), "mfs_plan_set_launch")
+
+    def set_progress(self, fn=None):
+        """Call fn(matvecs, active_systems, max_relres) after every GMRES
+        iteration of this plan's solves (see mfs_plan_set_progress); a truthy
+        return stops the solve early.  None removes it."""
+        if fn is None:
+            self._progress_cb = None
+            _check(lib().mfs_plan_set_progress(self._h, _PROGRESS_FN(), None), "mfs_plan_set_progress")
+            return
+
+        def tramp(_user, matvecs, active, relres):
+            return 1 if fn(int(matvecs), int(active), float(relres)) else 0
+
+        self._progress_cb = _PROGRESS_FN(tramp)  # kept alive while set
+        _check(lib().mfs_plan_set_progress(self._h, self._progress_cb, None), "mfs_plan_set_progress")
 
     def set_graph(self, enable: bool = True):
         """Replay the GMRES matvec from a captured hipGraph (see mfs.h)."""

@@ -6,6 +6,8 @@
   the FP64 oracle at GMRES tol 1e-10).  FP64 GPU at tol 1e-10: 1e-8; mixed at
   tol 1e-7: 1e-6; mixed at tol 1e-6: 1e-5 (the bar); mixed at the benchmark
   tolerance 1e-5 is reported.
+* ellipsoids_10000 (the paper's 10^4 Type T case): right-hand side and matvec on
+  1000 sampled rows (see the test).
 * ellipsoids_1000 (1000 spheroids): right-hand side and matvec on 2000
   sampled collocation rows, each row computed by the oracle from the same
   seeded inputs; and on the mixed solve, the exact net force and torque of
@@ -112,3 +114,72 @@ def test_ellipsoids_1000_solve_invariants():
         worst = max(worst, np.abs(FK - F[k]).max() / np.abs(F).max())
     print("iters", info["iters"], "relres", info["relres"], "net force/torque mismatch", worst)
     assert worst <= 1e-12
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_ellipsoids_10000_sampled_rows():
+    """The paper's large case (10^4 Type T ellipsoids, N = 658, M = 842, 5.5e13
+    off-body pairs per matvec): right-hand side and matvec on 1000 sampled
+    collocation rows, each computed by the oracle.  FP64: 1e-10 on a random
+    input, 1e-12 on the right-hand side; mixed: 2e-5 on a smooth field and on
+    the right-hand side (as for ellipsoids_1000)."""
+    import time
+    t0 = time.perf_counter()
+
+    def step(what):
+        print(f"[10^4 rows] {what} done, {time.perf_counter() - t0:.0f} s", flush=True)
+
+    mfs = _mfs()
+    wl = W.ellipsoids_10000(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    step("oracle set-up (one SVD)")
+    rows = np.sort(np.random.default_rng(86).choice(pr.X.shape[0], 1000, replace=False))
+    idx = pr._row_index(rows)
+    g = W.random_vector(pr.n_gamma, 87)
+    sm = W.smooth_vector(wl, 88)
+    ref_g = pr.matvec(g, rows=rows)
+    step("oracle matvec rows, random input")
+    ref_sm = pr.matvec(sm, rows=rows)
+    step("oracle matvec rows, smooth input")
+    ref_b, _ = pr.rhs(wl.net[0], rows=rows)
+    step("oracle right-hand side rows")
+    plan = mfs.Plan.from_workload(wl, mfs.MIXED)
+    step("GPU plan")
+    for prec, inp, ref, tol, tol_b in ((mfs.FP64, g, ref_g, 1e-10, 1e-12), (mfs.MIXED, sm, ref_sm, 2e-5, 2e-5)):
+        got = plan.matvec(_dev(inp), prec).cpu().numpy()[idx]
+        b, _ = plan.rhs(_dev(net_flat(wl)), prec=prec)
+        e = (rel_inf(got, ref), rel_inf(b.cpu().numpy()[idx], ref_b))
+        print("ellipsoids_10000", prec, "matvec rows err", e[0], "rhs rows err", e[1], flush=True)
+        assert e[0] <= tol and e[1] <= tol_b
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_ellipsoids_100_two_way_vs_stored_oracle():
+    """The 2-way test (eq. (2way)) at the benchmark size: resistance solve with
+    the stored rigid velocities U_ref (proxies at the resistance scale), then
+    the mobility solve with the resulting forces (proxies at 0.7); F, U and
+    eps_2way against the oracle's stored run (tests/golden/, FP64 at tol
+    1e-10).  FP64 at tol 1e-10: F and U within 1e-8; mixed at tol 1e-6:
+    within 1e-5; eps_2way within the same bound (it is a difference of U)."""
+    mfs = _mfs()
+    tab = np.loadtxt(os.path.join(GOLDEN, "ellipsoids_100_two_way.txt"))
+    U_ref, F_ref, U_2 = tab[:, :6], tab[:, 6:12], tab[:, 12:]
+    eps_ref = np.abs(U_2 - U_ref).max() / np.abs(U_ref).max()
+    wl = W.ellipsoids_100(W.STOKES)
+    wr = W.with_proxy_scale(wl, W.resistance_proxy_scale())
+    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-6, 1e-5)):
+        res = mfs.Plan.from_workload(wr, prec, formulation=mfs.RESISTANCE)
+        mob = mfs.Plan.from_workload(wl, prec)
+        F, ir = res.solve(_dev(U_ref), tol=tol)
+        U, im = mob.solve(F, tol=tol)
+        F, U = F.cpu().numpy(), U.cpu().numpy()
+        eps = np.abs(U - U_ref.reshape(-1)).max() / np.abs(U_ref).max()
+        e = (rel_inf(F, F_ref), rel_inf(U, U_2), abs(eps - eps_ref))
+        print(f"prec={prec} tol={tol:g} iters res {ir['iters']} mob {im['iters']} F err {e[0]:.2e} "
+              f"U err {e[1]:.2e} eps_2way {eps:.4e} (oracle {eps_ref:.4e})", flush=True)
+        assert ir["status"] == mfs.MFS_OK and im["status"] == mfs.MFS_OK
+        assert max(e) <= bar
+        res.close()
+        mob.close()

@@ -149,3 +149,25 @@ def test_gmres_status_and_errors():
     with pytest.raises(mfs.MfsError) as e:
         plan.gmres_solve(b, tol=-1.0)
     assert e.value.status == mfs.MFS_EINVAL
+
+
+def test_progress_callback_and_early_stop():
+    """mfs_plan_set_progress: one call per GMRES iteration with a falling
+    residual estimate; a non-zero return stops the solve (MFS_NOT_CONVERGED)."""
+    mfs = _mfs()
+    wl, pr = _case(W.STOKES)
+    plan = _plan(wl, mfs.FP64)
+    calls = []
+    plan.set_progress(lambda mv, act, rr: calls.append((mv, act, rr)) and False)
+    out, info = plan.solve(_dev(net_flat(wl)), tol=1e-8)
+    assert info["status"] == mfs.MFS_OK
+    assert len(calls) == info["iters"][0]
+    assert [c[0] for c in calls] == list(range(1, len(calls) + 1))
+    assert calls[-1][1] == 0 and calls[-1][2] <= 1e-8 and calls[0][2] > calls[-1][2]
+    plan.set_progress(lambda mv, act, rr: mv >= 3)
+    b, _ = plan.rhs(_dev(net_flat(wl)))
+    _, iters, relres, st = plan.gmres_solve(b, tol=1e-12)
+    assert st == mfs.MFS_NOT_CONVERGED and iters[0] == 3 and relres[0] > 1e-12
+    plan.set_progress(None)
+    _, iters, _, st = plan.gmres_solve(b, tol=1e-8)
+    assert st == mfs.MFS_OK and iters[0] > 3

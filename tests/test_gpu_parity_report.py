@@ -18,6 +18,8 @@ over the stacked output.  Bars (the same as the per-entry-point tests):
   gamma, lambda, sigma (solve)   1e-8      1e-3   FP64 solve at tol 1e-10; mixed at tol 1e-5
   U or phi (solve)               1e-8      1e-5   the outputs the method reports
   dJ/dc (adjoint, Stokes)        1e-8      1e-5   J = sum |U|^2; FP64 tol 1e-12, mixed tol 1e-8
+  resistance / capacitance (Section 2): rhs 1e-13 / 1e-13, S^+ apply and
+  A gamma as above, F or q from the solve 1e-8 / 1e-5
 
 The oracle's solves run at tol 1e-12.
 """
@@ -47,6 +49,10 @@ BARS = {
     "sigma": (1e-8, 1e-3),
     "U / phi": (1e-8, 1e-5),
     "dJ/dc": (1e-8, 1e-5),
+    "res: rhs b": (1e-13, 1e-13),
+    "res: S^+ apply": (1e-10, 5e-3),
+    "res: A gamma": (1e-10, 1e-4),
+    "res: F / q": (1e-8, 1e-5),
 }
 
 
@@ -139,6 +145,23 @@ def _rows(kind):
             assert st == mfs.MFS_OK
             add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
             plan.close()
+    # the Dirichlet formulation (capacitance / resistance, Section 2)
+    rp = O.ResistanceProblem.from_workload(wl)
+    data = np.random.default_rng(95).standard_normal((wl.n_body, 6) if kind == W.STOKES else wl.n_body)
+    rb_ref, _ = rp.rhs(data)
+    r_ref_p = np.concatenate([rp.pinv_apply(k, rp.gblock(g, k)) for k in range(wl.n_body)])
+    r_ref_A = rp.matvec(g)
+    r_sol = rp.solve(data, tol=1e-12)
+    for prec in (mfs.FP64, mfs.MIXED):
+        plan = mfs.Plan.from_workload(wl, prec, formulation=mfs.RESISTANCE)
+        b, _ = plan.rhs(_dev(data), prec=prec)
+        add("res: rhs b", prec, rel_inf(_np(b), rb_ref))
+        add("res: S^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), r_ref_p))
+        add("res: A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), r_ref_A))
+        out, info = plan.solve(_dev(data), tol=1e-10 if prec == mfs.FP64 else 1e-5)
+        assert info["status"] == mfs.MFS_OK
+        add("res: F / q", prec, rel_inf(_np(out), r_sol["out"]))
+        plan.close()
     return rows
 
 
