@@ -66,6 +66,7 @@ def _lib():
         lib.oracle_p2p_stokes.argtypes = [i64, d, i32, i64, d, i32, d, ctypes.c_double, ctypes.c_int, d]
         lib.oracle_p2p_grad.argtypes = [ctypes.c_int, i64, d, i32, d, i64, d, i32, d,
                                         ctypes.c_double, ctypes.c_int, d, d]
+        lib.oracle_p2p_field.argtypes = [ctypes.c_int, i64, d, i32, d, i64, d, i32, d, ctypes.c_int, d]
         lib.oracle_num_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -151,6 +152,26 @@ def p2p_grad(kind: int, X, trg_body, w, Y, src_body, s, mu=1.0, skip_same_body=T
                            _dp(s), float(mu), int(skip_same_body),
                            _dp(gx) if want_x else null, _dp(gy) if want_y else null)
     return gx, gy
+
+
+FIELD_PRESSURE, FIELD_TRACTION, FIELD_LAPLACE_GRADIENT = 0, 1, 2
+
+
+def p2p_field(field: int, X, trg_body, Y, src_body, s, normal=None, skip_same_body: bool = False):
+    """Derived fields of the representation at targets X (plain C loops):
+    Stokes pressure p = (1/(8 pi)) sum Pi . f with Pi = 2 d / r^3 (Section 2.2);
+    Stokes traction sigma . n (the Stokeslet's stress, eq. (traction)); Laplace
+    gradient of u.  Returns (n,) for the pressure, (n, 3) otherwise."""
+    X = np.ascontiguousarray(X, np.float64)
+    Y = np.ascontiguousarray(Y, np.float64)
+    s = np.ascontiguousarray(s, np.float64)
+    tb = np.ascontiguousarray(trg_body, np.int32)
+    sb = np.ascontiguousarray(src_body, np.int32)
+    nrm = np.ascontiguousarray(normal if normal is not None else np.zeros_like(X), np.float64)
+    out = np.zeros(X.shape[0]) if field == FIELD_PRESSURE else np.zeros((X.shape[0], 3))
+    _lib().oracle_p2p_field(int(field), X.shape[0], _dp(X), _ip(tb), _dp(nrm), Y.shape[0], _dp(Y), _ip(sb),
+                            _dp(s), int(skip_same_body), _dp(out))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -455,6 +476,29 @@ class Problem:
         gamma, iters, hist = gmres(self.matvec, b, tol, max_iter)
         out, lam, sigma = self.extract(gamma, s0)
         return dict(out=out, gamma=gamma, lam=lam, sigma=sigma, b=b, s0=s0, iters=iters, hist=hist)
+
+    # -- surface residual (eq. (residual)) ------------------------------------------------
+    def surface_residual(self, sigma: np.ndarray, out: np.ndarray, test_local) -> np.ndarray:
+        """eps_res(x) = |u(x) - g(x)| / |g(x)| at test points on every body
+        surface: u is the representation with the full strengths sigma over all
+        proxies (self included), g the body's rigid motion v + omega x (x - c)
+        (Stokes) or its potential (Laplace) from the solve's outputs.
+        test_local: (n_t, 3) points on the surface of the shape, body frame
+        (one shape for all bodies).  Returns eps stacked body by body."""
+        pts, ids = [], []
+        for k, b in enumerate(self.bodies):
+            pts.append(b.centre + np.asarray(test_local) @ b.rot.T)
+            ids.append(np.full(len(test_local), k, np.int32))
+        Xt, tb = np.concatenate(pts), np.concatenate(ids)
+        s = sigma.reshape(-1, 3) if self.kind == STOKES else sigma
+        u = p2p(self.kind, Xt, tb, self.Y, self.src_body, s, self.mu, False)
+        out = np.asarray(out, np.float64)
+        if self.kind == LAPLACE:
+            g = out[tb]
+            return np.abs(u - g) / np.abs(g)
+        c = np.stack([self.bodies[k].centre for k in tb])
+        g = out[tb, :3] + np.cross(out[tb, 3:], Xt - c)
+        return np.linalg.norm(u - g, axis=1) / np.linalg.norm(g, axis=1)
 
     # -- adjoint (derived from the square system; the paper has no gradients) ----------
     def matvec_T(self, w: np.ndarray) -> np.ndarray:

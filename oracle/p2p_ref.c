@@ -173,3 +173,56 @@ int oracle_num_threads(void)
     }
     return n;
 }
+
+/*
+ * Derived fields of the representation at arbitrary targets (same pair sets):
+ *   field 0, Stokes pressure (Section 2.2):  p(x_i) = (1/(8 pi)) sum_j Pi(x_i - y_j) . f_j,
+ *            with Pi(d) = 2 d / |d|^3;
+ *   field 1, Stokes traction sigma(x_i) . n_i, with the stress of the Stokeslet
+ *            (sigma = -p I + mu (grad u + grad u^T), eq. (traction)):
+ *            sigma_ab(x_i) = -(3 / (4 pi)) sum_j d_a d_b (d . f_j) / |d|^5,
+ *            and n_i the given unit vector at target i;
+ *   field 2, Laplace gradient grad u(x_i) = -sum_j q_j d / (4 pi |d|^3).
+ * d = x_i - y_j.  out is [n_trg] (field 0) or [n_trg][3].
+ */
+void oracle_p2p_field(int field, int64_t n_trg, const double *x, const int32_t *trg_body, const double *normal,
+                      int64_t n_src, const double *y, const int32_t *src_body, const double *s,
+                      int skip_same_body, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_trg; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n_src; ++j) {
+            if (skip_same_body && trg_body[i] == src_body[j])
+                continue;
+            double d[3] = {x[3 * i + 0] - y[3 * j + 0], x[3 * i + 1] - y[3 * j + 1], x[3 * i + 2] - y[3 * j + 2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double r = sqrt(r2);
+            if (field == 0) {
+                const double *f = s + 3 * j;
+                double Pi[3] = {2.0 * d[0] / (r * r2), 2.0 * d[1] / (r * r2), 2.0 * d[2] / (r * r2)};
+                acc[0] += (Pi[0] * f[0] + Pi[1] * f[1] + Pi[2] * f[2]) / (8.0 * PI);
+            } else if (field == 1) {
+                const double *f = s + 3 * j;
+                const double *n = normal + 3 * i;
+                double sig[3][3];
+                double df = d[0] * f[0] + d[1] * f[1] + d[2] * f[2];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        sig[a][b] = -3.0 / (4.0 * PI) * d[a] * d[b] * df / (r2 * r2 * r);
+                for (int a = 0; a < 3; ++a)
+                    acc[a] += sig[a][0] * n[0] + sig[a][1] * n[1] + sig[a][2] * n[2];
+            } else {
+                for (int a = 0; a < 3; ++a)
+                    acc[a] += -s[j] * d[a] / (4.0 * PI * r * r2);
+            }
+        }
+        if (field == 0) {
+            out[i] = acc[0];
+        } else {
+            out[3 * i + 0] = acc[0];
+            out[3 * i + 1] = acc[1];
+            out[3 * i + 2] = acc[2];
+        }
+    }
+}

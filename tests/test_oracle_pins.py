@@ -23,6 +23,11 @@ independently of the oracle's own formulas (CPU only).
   (qkgauss), (force_eq); the matvec of eq. (2sysprec) assembled from dense
   blocks; symmetry and positivity of the resistance matrix; the 2-way error
   (eq. (2way)) small and falling with N.
+* Derived fields: Stokes' translating sphere (pressure outside, uniform
+  surface traction), the traction equal to the stress from finite
+  differences of the velocity plus the pressure, a charged sphere's field,
+  and the surface residual of eq. (residual) small, falling with N and large
+  for wrong data.
 * A planted mistake in the oracle makes a pin fail.
 """
 import numpy as np
@@ -406,6 +411,85 @@ def test_two_way_error_small_and_converging(kind):
         assert r["iters_res"] >= r["iters_mob"]   # mobility needs fewer iterations (Section 4)
     assert eps[1] < eps[0] / 5
     assert eps[1] < (1e-4 if kind == W.STOKES else 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# derived fields: pressure, traction, field gradient, surface residual
+# ---------------------------------------------------------------------------
+
+def _sphere_dirs(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_translating_sphere_pressure_and_traction():
+    """Stokes' translating sphere (textbook): p = (3 mu a / 2) U.x / r^3 outside,
+    and the traction sigma . n on the surface (n outward) is -(3 mu / (2 a)) U."""
+    wl = W.single_sphere(W.STOKES)
+    U = np.array([1.0, 0.3, -0.2, 0.0, 0.0, 0.0])
+    rp = O.ResistanceProblem.from_workload(wl)
+    lam = rp.solve(U[None], tol=1e-13)["lam"].reshape(-1, 3)
+    dirs = _sphere_dirs(60, 3)
+    zero_t, zero_s = np.zeros(60, np.int32), np.zeros(len(rp.Y), np.int32)
+    for R, tol in ((1.5, 1e-4), (3.0, 1e-5)):
+        X = R * dirs
+        p = O.p2p_field(O.FIELD_PRESSURE, X, zero_t, rp.Y, zero_s, lam)
+        pex = 1.5 * (X @ U[:3]) / R ** 3
+        assert np.abs(p - pex).max() < tol * np.abs(pex).max()
+    T = O.p2p_field(O.FIELD_TRACTION, dirs, zero_t, rp.Y, zero_s, lam, normal=dirs)
+    assert np.abs(T + 1.5 * U[:3]).max() < 1e-2 * 1.5 * np.abs(U).max()
+
+
+def test_traction_equals_stress_from_finite_differences():
+    """sigma . n = (-p I + mu (grad u + grad u^T)) n (eq. (traction)) with grad u
+    by central differences of the velocity sums, at points between bodies."""
+    wl = W.small_cluster(3, W.STOKES, 40, 90, seed=12, axes=(1.0, 1.0, 1.0), gap=1.0)
+    Y, sb = wl.world_points("src")
+    f = np.random.default_rng(13).standard_normal((Y.shape[0], 3))
+    X = wl.centre.mean(0) + 0.3 * np.random.default_rng(14).standard_normal((8, 3))
+    X = X[np.min(np.linalg.norm(X[:, None] - wl.centre[None], axis=-1), axis=1) > 1.2]
+    n = _sphere_dirs(X.shape[0], 15)
+    tb = np.full(X.shape[0], -1, np.int32)
+    h = 1e-5
+    grad = np.zeros((X.shape[0], 3, 3))
+    for b in range(3):
+        e = np.zeros(3)
+        e[b] = h
+        up = O.p2p(W.STOKES, X + e, tb, Y, sb, f, 1.0, False)
+        um = O.p2p(W.STOKES, X - e, tb, Y, sb, f, 1.0, False)
+        grad[:, :, b] = (up - um) / (2 * h)
+    p = O.p2p_field(O.FIELD_PRESSURE, X, tb, Y, sb, f)
+    sig = -p[:, None, None] * np.eye(3) + grad + np.swapaxes(grad, 1, 2)
+    want = np.einsum("iab,ib->ia", sig, n)
+    T = O.p2p_field(O.FIELD_TRACTION, X, tb, Y, sb, f, normal=n)
+    assert np.abs(T - want).max() < 1e-7 * np.abs(want).max()
+    # and the pressure closes the Stokes equations' divergence-free flow: trace(grad u) = 0
+    assert np.abs(np.trace(grad, axis1=1, axis2=2)).max() < 1e-7 * np.abs(grad).max()
+
+
+def test_charged_sphere_field_gradient():
+    """A sphere carrying charge q: grad u = -q x / (4 pi r^3) outside (Coulomb)."""
+    pr = O.Problem.from_workload(W.single_sphere(W.LAPLACE))
+    sig = pr.solve(np.array([2.0]), tol=1e-13)["sigma"]
+    X = 1.7 * _sphere_dirs(60, 4)
+    g = O.p2p_field(O.FIELD_LAPLACE_GRADIENT, X, np.zeros(60, np.int32), pr.Y, np.zeros(len(pr.Y), np.int32), sig)
+    want = -2.0 * X / (4 * np.pi * 1.7 ** 3)
+    assert np.abs(g - want).max() < 1e-5 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_surface_residual_small_and_converging(kind):
+    """eps_res (eq. (residual)) at 1732 surface points of one sphere: small, falls
+    with N, and a wrong rigid motion / potential makes it large."""
+    res = []
+    for n in (100, 300):
+        wl = W.single_sphere(kind, n_src=n, n_trg=2 * n)
+        pr = O.Problem.from_workload(wl)
+        sol = pr.solve(wl.net[0], tol=1e-13)
+        res.append(pr.surface_residual(sol["sigma"], sol["out"], W.fibonacci_sphere(1732, 1.0)).max())
+    assert res[1] < 1e-3 and res[1] < res[0] / 3
+    wrong = np.asarray(sol["out"], np.float64) * 1.01
+    assert pr.surface_residual(sol["sigma"], wrong, W.fibonacci_sphere(1732, 1.0)).max() > 5e-3
 
 
 # ---------------------------------------------------------------------------
