@@ -123,6 +123,31 @@ int mfs_p2p_stokes_backward(int64_t n_sys, const int64_t *sys_body_ptr, const in
                             double *grad_trg_xyz, double *grad_src_xyz, double mu, int flags, int prec,
                             void *stream);
 
+/* Derived fields of the representation at arbitrary targets (same structure
+ * arguments, flags and precision as the pair sums above; d = x_i - y_j, r = |d|).
+ *   mfs_p2p_stokes_pressure: out_p [n_trg] = (1/(8 pi)) sum_j Pi(d) . f_j with
+ *     Pi(d) = 2 d / r^3 (Section 2.2, the pressure of the representation).
+ *   mfs_p2p_stokes_traction: out_t [n_trg][3] = sigma(x_i) . n_i, the stress
+ *     sigma = -p I + mu (grad u + grad u^T) of the Stokeslet sum (eq. (traction)),
+ *     sigma_ab = -(3/(4 pi)) sum_j d_a d_b (d . f_j) / r^5 (independent of mu);
+ *     trg_normal [n_trg][3] [device] holds the unit vectors n_i.  With n the
+ *     outward normal of a body, the integral of the traction over its surface is
+ *     the force of the fluid on the body, -K_N^T lambda.
+ *   mfs_p2p_laplace_gradient: out_g [n_trg][3] = grad u(x_i) =
+ *     -(1/(4 pi)) sum_j q_j d / r^3.
+ * Derived from the kernels of Section 2 (the paper states the pressure and
+ * the traction definition, not these sums). */
+int mfs_p2p_stokes_pressure(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                            const double *src_f, double *out_p, int flags, int prec, void *stream);
+int mfs_p2p_stokes_traction(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *trg_normal,
+                            const double *src_xyz, const double *src_f, double *out_t, int flags, int prec,
+                            void *stream);
+int mfs_p2p_laplace_gradient(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                             const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                             const double *src_q, double *out_g, int flags, int prec, void *stream);
+
 /* -------------------------------------------------------------------------
  * Plans.  A plan owns everything the solve reuses: device geometry, the
  * per-shape pseudo-inverse factors of S_L = S^(kk)(I - L) + L_r (Section 3.3),
@@ -249,6 +274,21 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
                        double *grad_centre, double tol, int32_t max_iter, int32_t max_refine,
                        int32_t *iters, double *relres, void *stream);
 /* (MFS_MOBILITY plans only; MFS_EUNSUPPORTED for MFS_RESISTANCE.) */
+
+/* Surface residual (eq. (residual)): eps(x) = |u(x) - g(x)| / |g(x)| at test
+ * points on every body surface, with u the representation of the full
+ * strengths sigma [device, lambda layout, e.g. from mfs_extract] over all
+ * proxies of the system (same-body pairs included) and g the body's rigid
+ * motion v + omega x (x - c) (Stokes) or its potential phi (Laplace) from
+ * motion [device, net layout: the solve's output, or the Dirichlet data of a
+ * resistance solve].  Test points per shape in the shape frame:
+ * shape_n_test [host][n_shape], shape_test [host] concatenated, sum x 3.
+ * eps [device] body by body; u_test [device, optional] receives u at the
+ * points (3 or 1 values per point).  prec selects the pair arithmetic.
+ * Writes the pair-sum source records of the plan (the next matvec rewrites
+ * them).  Synchronous. */
+int mfs_surface_residual(mfs_plan plan, const double *sigma, const double *motion, const int32_t *shape_n_test,
+                         const double *shape_test, double *eps, double *u_test, int prec, void *stream);
 
 /* Instrumentation.  With timing enabled, every pair-sum launch of the plan's
  * matvec (the dominant kernel) is bracketed by HIP events recorded on the

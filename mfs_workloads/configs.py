@@ -278,6 +278,17 @@ def type_t_cluster(n_body: int, kind: int, seed: int, delta: float = 0.2, n_v: i
                            f"type_t_{n_body}_{kind}_{seed}")
 
 
+def surface_test_points(shape: Shape, n: int = 1732) -> np.ndarray:
+    """n points on the physical surface of a shape (body frame) for the surface
+    residual; the paper uses 1732 per particle (Section 4.2).  Spheroids: the
+    equal-area Fibonacci lattice; other ellipsoids: the ring grid with n nodes."""
+    a, b, c = (float(x) for x in shape.axes)
+    if abs(a - b) < 1e-15:
+        return fibonacci_spheroid(n, a, c)
+    n_v = int(round((-3.9 + math.sqrt(3.9 ** 2 + 4 * 0.44 * (n - 17))) / (2 * 0.44)))
+    return ellipsoid_ring_grid(a, b, c, n_v, n_total=n)
+
+
 def with_proxy_scale(wl: Workload, scale: float) -> Workload:
     """The same suspension with every shape's proxies regenerated on the
     surface scaled by `scale` (same count).  For the 2-way error, which pairs

@@ -234,6 +234,54 @@ int p2p_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const i
     return MFS_OK;
 }
 
+// Derived fields (pressure, traction, Laplace gradient) of standalone inputs.
+int field_standalone(int field, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                     const int64_t *body_src_ptr, const double *trg_xyz, const double *trg_normal,
+                     const double *src_xyz, const double *str, double *out, int flags, int prec, void *stream) {
+    int64_t nb, nt, ns;
+    MFS_TRY(check_structure(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, &nb, &nt, &ns));
+    MFS_TRY(check_prec(prec));
+    if (flags & ~(MFS_SKIP_SAME_BODY | MFS_ACCUMULATE)) return fail(MFS_EINVAL, "unknown flags");
+    if ((nt > 0 && (!trg_xyz || !out)) || (ns > 0 && (!src_xyz || !str)))
+        return fail(MFS_EINVAL, "NULL data pointer");
+    if (field == MFS_FIELD_TRACTION && nt > 0 && !trg_normal) return fail(MFS_EINVAL, "NULL target normals");
+    if (nt == 0) return MFS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int kind = field == MFS_FIELD_LAPLACE_GRADIENT ? MFS_LAPLACE : MFS_STOKES;
+    Workspace &ws = workspace();
+    MFS_TRY(standalone_geometry(ws, nb, nt, ns, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, prec, s));
+    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
+                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
+    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
+    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), str, prec,
+                            ws.src_ops.ptr, s));
+    const int dim = field == MFS_FIELD_PRESSURE ? 1 : 3;
+    std::vector<int64_t> out_ptr(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
+    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
+    P2PPlan pp;
+    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), 1.0, 1,
+                            2048, s));
+    P2PLaunch L;
+    L.prec = prec;
+    L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
+    L.accumulate = (flags & MFS_ACCUMULATE) != 0;
+    L.centre = ws.centre.as<double>();
+    L.trg_body = ws.trg_body.as<int32_t>();
+    L.src_ptr = ws.src_ptr.as<int32_t>();
+    L.trg_off = ws.trg_off.ptr;
+    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
+    L.out = out;
+    L.n_val = dim * nt;
+    if (pp.n_split > 1) {
+        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * L.n_val * sizeof(double)));
+        L.partial = ws.partial.as<double>();
+    }
+    MFS_TRY(launch_field(field, pp, L, trg_normal, nt, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    return MFS_OK;
+}
+
 // Position gradient of the pairing over one orientation: lanes carry lane_vec
 // ([n_lane][dim]), sources carry src_str; out_grad [n_lane][3].
 int p2p_grad_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *lane_ptr,
@@ -316,7 +364,9 @@ struct mfs_plan_s {
     int64_t n_sys = 0, n_body = 0;
     std::vector<int64_t> sys_body_ptr;
     std::vector<int32_t> sys_kind;
-    std::vector<int32_t> kind, n_src, n_trg, factor_of_body;
+    std::vector<int32_t> kind, n_src, n_trg, factor_of_body, shape_of_body;
+    std::vector<double> rot_h;  // [n_body][9]
+    int64_t n_shape = 0;
     std::vector<int64_t> gam_off, lam_off, net_off;  // n_body + 1 entries
     std::vector<int64_t> src_row, trg_row;           // n_body + 1 entries
     int64_t n_gamma = 0, n_lambda = 0, n_net = 0, n_srcp = 0, n_trgp = 0;
@@ -710,6 +760,28 @@ int mfs_p2p_stokes_backward(int64_t n_sys, const int64_t *sys_body_ptr, const in
                                    trg_w, grad_src_f, grad_trg_xyz, grad_src_xyz, mu, flags, prec, stream);
 }
 
+int mfs_p2p_stokes_pressure(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                            const double *src_f, double *out_p, int flags, int prec, void *stream) {
+    return field_standalone(MFS_FIELD_PRESSURE, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, nullptr,
+                            src_xyz, src_f, out_p, flags, prec, stream);
+}
+
+int mfs_p2p_stokes_traction(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                            const int64_t *body_src_ptr, const double *trg_xyz, const double *trg_normal,
+                            const double *src_xyz, const double *src_f, double *out_t, int flags, int prec,
+                            void *stream) {
+    return field_standalone(MFS_FIELD_TRACTION, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, trg_normal,
+                            src_xyz, src_f, out_t, flags, prec, stream);
+}
+
+int mfs_p2p_laplace_gradient(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                             const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                             const double *src_q, double *out_g, int flags, int prec, void *stream) {
+    return field_standalone(MFS_FIELD_LAPLACE_GRADIENT, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz,
+                            nullptr, src_xyz, src_q, out_g, flags, prec, stream);
+}
+
 int mfs_plan_destroy(mfs_plan plan) {
     if (!plan) return MFS_OK;
     (void)hipDeviceSynchronize();
@@ -754,6 +826,9 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     std::unique_ptr<mfs_plan_s> p(new mfs_plan_s());
     p->prec = d->precision;
     p->formulation = d->formulation;
+    p->n_shape = d->n_shape;
+    p->shape_of_body.assign(d->shape_of_body, d->shape_of_body + nb);
+    p->rot_h.assign(d->rot, d->rot + 9 * nb);
     p->mu = d->mu;
     p->n_sys = d->n_sys;
     p->n_body = nb;
@@ -1681,5 +1756,85 @@ extern "C" int mfs_plan_set_launch(mfs_plan p, int32_t targets_per_lane, int32_t
     p->tuned_tpl = targets_per_lane;
     p->tuned_min_items = work_items;
     p->tuned_persistent = persistent != 0;
+    return MFS_OK;
+}
+
+extern "C" int mfs_surface_residual(mfs_plan p, const double *sigma, const double *motion,
+                                    const int32_t *shape_n_test, const double *shape_test, double *eps, double *u_test,
+                                    int prec, void *stream) {
+    using namespace mfs;
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    MFS_TRY(check_prec(prec));
+    if (!sigma || !motion || !shape_n_test || !shape_test || !eps) return fail(MFS_EINVAL, "NULL argument");
+    const int64_t nb = p->n_body;
+    std::vector<int64_t> so(p->n_shape + 1, 0);
+    for (int64_t sh = 0; sh < p->n_shape; ++sh) {
+        if (shape_n_test[sh] < 0) return fail(MFS_EINVAL, "negative test point count");
+        so[sh + 1] = so[sh] + shape_n_test[sh];
+    }
+    for (int64_t q = 0; q < 3 * so[p->n_shape]; ++q)
+        if (!std::isfinite(shape_test[q])) return fail(MFS_EINVAL, "non-finite test point");
+    // test points of every body in world axes relative to its centre, body by body
+    std::vector<int64_t> tptr(nb + 1, 0), uptr(nb + 1, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t m = shape_n_test[p->shape_of_body[b]];
+        tptr[b + 1] = tptr[b] + m;
+        uptr[b + 1] = uptr[b] + (p->kind[b] == MFS_STOKES ? 3 : 1) * m;
+    }
+    const int64_t n = tptr[nb], nu = uptr[nb];
+    if (n == 0) return MFS_OK;
+    if (n > INT32_MAX / 2) return fail(MFS_EINVAL, "too many test points");
+    std::vector<double> o64(4 * n);
+    std::vector<float> o32(4 * n);
+    std::vector<int32_t> tb(n);
+    std::vector<int64_t> uoff(n);
+    for (int64_t b = 0; b < nb; ++b) {
+        const double *R = p->rot_h.data() + 9 * b;
+        const double *loc = shape_test + 3 * so[p->shape_of_body[b]];
+        const int dim = p->kind[b] == MFS_STOKES ? 3 : 1;
+        for (int64_t i = tptr[b]; i < tptr[b + 1]; ++i) {
+            const double *q = loc + 3 * (i - tptr[b]);
+            for (int a = 0; a < 3; ++a) {
+                const double v = R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2];
+                o64[4 * i + a] = v;
+                o32[4 * i + a] = (float)v;
+            }
+            o64[4 * i + 3] = 0.0;
+            o32[4 * i + 3] = 0.f;
+            tb[i] = (int32_t)b;
+            uoff[i] = uptr[b] + dim * (i - tptr[b]);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf d_o64, d_o32, d_tb, d_uoff, d_u, d_part;
+    MFS_TRY(upload_vec(d_o64, o64, s));
+    MFS_TRY(upload_vec(d_o32, o32, s));
+    MFS_TRY(upload_vec(d_tb, tb, s));
+    MFS_TRY(upload_vec(d_uoff, uoff, s));
+    double *u = u_test;
+    if (!u) {
+        MFS_TRY(d_u.reserve(nu * sizeof(double)));
+        u = d_u.as<double>();
+    }
+    // the representation with the full strengths over all proxies, self included
+    MFS_TRY(set_fwd_strength(p, sigma, prec, s));
+    std::vector<int64_t> src_row(p->src_row);
+    P2PPlan pp;
+    MFS_TRY(build_p2p_items(pp, p->n_sys, p->sys_body_ptr.data(), tptr.data(), src_row.data(), uptr.data(),
+                            p->kind.data(), p->mu, 1, 2048, s));
+    P2PLaunch L = fwd_launch(p, prec);
+    L.trg_off = prec == MFS_MIXED ? d_o32.ptr : d_o64.ptr;
+    L.trg_body = d_tb.as<int32_t>();
+    L.skip_same = false;
+    L.out = u;
+    L.n_val = nu;
+    if (pp.n_split > 1) {
+        MFS_TRY(d_part.reserve((size_t)pp.n_split * nu * sizeof(double)));
+        L.partial = d_part.as<double>();
+    }
+    MFS_TRY(launch_p2p(pp, L, s));
+    MFS_TRY(launch_residual(n, d_tb.as<int32_t>(), p->d_kind.as<int32_t>(), p->d_net_off.as<int64_t>(),
+                            d_o64.as<double>(), u, d_uoff.as<int64_t>(), motion, eps, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
     return MFS_OK;
 }

@@ -145,6 +145,16 @@ int launch_fill_body_ids(int64_t n_body, const int32_t *ptr, int32_t *ids, hipSt
 // forward output, gradient [n_lane][3].
 int launch_p2p_grad(const P2PPlan &pp, const P2PLaunch &L, const double *lane_vec, int64_t n_lane, hipStream_t s);
 
+// Derived fields of the representation (field_kernels.hip): items of one target
+// per lane; L.srcS (pressure, traction) or L.srcL (Laplace gradient) hold the
+// sources; out [n_trg] (pressure) or [n_trg][3]; normal [n_trg][3] (traction).
+enum { MFS_FIELD_PRESSURE = 0, MFS_FIELD_TRACTION = 1, MFS_FIELD_LAPLACE_GRADIENT = 2 };
+int launch_field(int field, const P2PPlan &pp, const P2PLaunch &L, const double *normal, int64_t n_trg,
+                 hipStream_t s);
+// eps[i] = |u_i - g_i| / |g_i| with g the rigid motion (or potential) of body[i] at offset off64[i]
+int launch_residual(int64_t n, const int32_t *body, const int32_t *kind, const int64_t *net_off, const double *off64,
+                    const double *u, const int64_t *u_off, const double *motion, double *eps, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Block (one-body) kernels (block_kernels.hip)
 // ---------------------------------------------------------------------------

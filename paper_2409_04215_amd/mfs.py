@@ -81,6 +81,11 @@ def lib():
         L.mfs_plan_last_solve.argtypes = [_vp, _i32p, _i32p]
         L.mfs_plan_set_launch.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]
         L.mfs_plan_set_progress.argtypes = [_vp, _PROGRESS_FN, _vp]
+        # (n_sys, structure, trg_xyz, src_xyz | trg_normal) + remaining pointers, flags, prec, stream
+        L.mfs_p2p_stokes_pressure.argtypes = geo + [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+        L.mfs_p2p_stokes_traction.argtypes = geo + [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+        L.mfs_p2p_laplace_gradient.argtypes = geo + [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+        L.mfs_surface_residual.argtypes = [_vp, _vp, _vp, _i32p, _dp, _vp, _vp, ctypes.c_int, _vp]
         L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
         L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, _i32p, _dp, _vp]
@@ -155,6 +160,39 @@ def p2p_stokes(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f
     return out
 
 
+def p2p_stokes_pressure(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f, flags=0, prec=MIXED,
+                        out=None, stream=None) -> torch.Tensor:
+    """p_i = (1/(8 pi)) sum_j Pi(x_i - y_j) . f_j (see mfs.h)."""
+    keep = _geo(sys_body_ptr, body_trg_ptr, body_src_ptr)
+    if out is None:
+        out = torch.zeros(trg_xyz.shape[0], dtype=torch.float64, device=trg_xyz.device)
+    _check(lib().mfs_p2p_stokes_pressure(*keep[3], _ptr(trg_xyz), _ptr(src_xyz), _ptr(src_f), _ptr(out), flags,
+                                         prec, _stream(stream)), "mfs_p2p_stokes_pressure")
+    return out
+
+
+def p2p_stokes_traction(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, trg_normal, src_xyz, src_f, flags=0,
+                        prec=MIXED, out=None, stream=None) -> torch.Tensor:
+    """sigma(x_i) . n_i of the Stokeslet sum (see mfs.h)."""
+    keep = _geo(sys_body_ptr, body_trg_ptr, body_src_ptr)
+    if out is None:
+        out = torch.zeros(trg_xyz.shape[0], 3, dtype=torch.float64, device=trg_xyz.device)
+    _check(lib().mfs_p2p_stokes_traction(*keep[3], _ptr(trg_xyz), _ptr(trg_normal), _ptr(src_xyz), _ptr(src_f),
+                                         _ptr(out), flags, prec, _stream(stream)), "mfs_p2p_stokes_traction")
+    return out
+
+
+def p2p_laplace_gradient(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_q, flags=0, prec=MIXED,
+                         out=None, stream=None) -> torch.Tensor:
+    """grad u(x_i) of the Laplace sum (see mfs.h)."""
+    keep = _geo(sys_body_ptr, body_trg_ptr, body_src_ptr)
+    if out is None:
+        out = torch.zeros(trg_xyz.shape[0], 3, dtype=torch.float64, device=trg_xyz.device)
+    _check(lib().mfs_p2p_laplace_gradient(*keep[3], _ptr(trg_xyz), _ptr(src_xyz), _ptr(src_q), _ptr(out), flags,
+                                          prec, _stream(stream)), "mfs_p2p_laplace_gradient")
+    return out
+
+
 def p2p_laplace_backward(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_q, trg_w,
                          want=("src", "trg_xyz", "src_xyz"), flags=SKIP_SAME_BODY, prec=MIXED, stream=None):
     keep = _geo(sys_body_ptr, body_trg_ptr, body_src_ptr)
@@ -201,6 +239,7 @@ class Plan:
         self.shape_of_body = np.ascontiguousarray(np.asarray(shape_of_body, dtype=np.int32))
         self.shape_n_src = np.array([len(s) for s in shape_src], dtype=np.int32)
         self.shape_n_trg = np.array([len(s) for s in shape_trg], dtype=np.int32)
+        self.body_kind = np.repeat(self.sys_kind, np.diff(self.sys_body_ptr))
         self.shape_src = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64) for s in shape_src]))
         self.shape_trg = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64) for s in shape_trg]))
         d = PlanDesc()
@@ -300,6 +339,24 @@ class Plan:
         gamma, iters, relres, st = self.gmres_solve(b, tol, max_iter, max_refine, stream=stream)
         out, _ = self.extract(gamma, s0, stream=stream)
         return out, dict(gamma=gamma, s0=s0, b=b, iters=iters, relres=relres, status=st)
+
+    def surface_residual(self, sigma: torch.Tensor, motion: torch.Tensor, test_points, prec: Optional[int] = None,
+                         want_u: bool = False, stream=None):
+        """eps = |u - g| / |g| at test points on every body (see mfs_surface_residual).
+        test_points: one (n, 3) array in the shape frame per shape (or one array
+        for a one-shape plan).  Returns eps [n_test_total] (and u if want_u)."""
+        pts = [test_points] if not isinstance(test_points, (list, tuple)) else list(test_points)
+        counts = np.array([len(p) for p in pts], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1, 3) for p in pts]))
+        per_body = counts[self.shape_of_body]
+        dims = np.where(self.body_kind == STOKES, 3, 1)
+        eps = self._new(int(per_body.sum()))
+        u = self._new(int((per_body * dims).sum())) if want_u else None
+        _check(lib().mfs_surface_residual(self._h, _ptr(sigma), _ptr(motion), counts.ctypes.data_as(_i32p),
+                                          flat.ctypes.data_as(_dp), _ptr(eps), _ptr(u),
+                                          self.precision if prec is None else prec, _stream(stream)),
+               "mfs_surface_residual")
+        return (eps, u) if want_u else eps
 
     def set_timing(self, enable: bool = True):
         """Bracket every matvec pair-sum launch with HIP events (see mfs.h)."""

@@ -1,0 +1,126 @@
+"""Derived fields (pressure, traction, Laplace gradient) and the surface
+residual (eq. (residual)) on the GPU against the oracle's plain loops.
+
+Tolerances (rel_inf = max|x - ref| / max|ref|):
+* FP64: 1e-12 (pressure, gradient), 1e-11 (traction: three more products).
+* Mixed: FP32 pairs with FP64 accumulation per run of <= 64 sources, as for
+  the pair sums (2e-5); traction 5e-5 (r^-5 and two dot products per pair).
+* Surface residual: the GPU evaluates eps from the oracle's own strengths and
+  rigid motions; |eps_gpu - eps_ref| <= 1e-10 (FP64) and 2e-6 (mixed: the
+  FP32 pair sums err by ~1e-7 of |u|, and |u| ~ |g| on the surface).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import net_flat, rel_inf, structure
+
+pytestmark = pytest.mark.gpu
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64), dtype=torch.float64, device="cuda")
+
+
+def _unit(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("skip", [False, True])
+def test_field_sums_match_oracle(skip):
+    mfs = _mfs()
+    wl = W.small_cluster(5, W.STOKES, 45, 301, seed=111)
+    sp, tp, pp = structure(wl)
+    X, tb = wl.world_points("trg")
+    X = X + 0.05 * np.random.default_rng(112).standard_normal(X.shape)  # near, not on, the surfaces
+    Y, sb = wl.world_points("src")
+    rng = np.random.default_rng(113)
+    f = rng.standard_normal((Y.shape[0], 3))
+    q = rng.standard_normal(Y.shape[0])
+    n = _unit(X.shape[0], 114)
+    ref_p = O.p2p_field(O.FIELD_PRESSURE, X, tb, Y, sb, f, skip_same_body=skip)
+    ref_t = O.p2p_field(O.FIELD_TRACTION, X, tb, Y, sb, f, normal=n, skip_same_body=skip)
+    ref_g = O.p2p_field(O.FIELD_LAPLACE_GRADIENT, X, tb, Y, sb, q, skip_same_body=skip)
+    flags = mfs.SKIP_SAME_BODY if skip else 0
+    for prec, tp_, tt_, tg_ in ((mfs.FP64, 1e-12, 1e-11, 1e-12), (mfs.MIXED, 2e-5, 5e-5, 2e-5)):
+        p = mfs.p2p_stokes_pressure(sp, tp, pp, _dev(X), _dev(Y), _dev(f), flags, prec)
+        t = mfs.p2p_stokes_traction(sp, tp, pp, _dev(X), _dev(n), _dev(Y), _dev(f), flags, prec)
+        g = mfs.p2p_laplace_gradient(sp, tp, pp, _dev(X), _dev(Y), _dev(q), flags, prec)
+        e = (rel_inf(p.cpu().numpy(), ref_p), rel_inf(t.cpu().numpy(), ref_t), rel_inf(g.cpu().numpy(), ref_g))
+        print("skip", skip, "prec", prec, "pressure, traction, gradient", e)
+        assert e[0] <= tp_ and e[1] <= tt_ and e[2] <= tg_
+    # ACCUMULATE adds into out
+    base = torch.ones(X.shape[0], dtype=torch.float64, device="cuda")
+    mfs.p2p_stokes_pressure(sp, tp, pp, _dev(X), _dev(Y), _dev(f), flags | mfs.ACCUMULATE, mfs.FP64, out=base)
+    assert rel_inf(base.cpu().numpy() - 1.0, ref_p) <= 1e-12
+
+
+def test_fields_two_systems_do_not_interact():
+    mfs = _mfs()
+    a = W.small_cluster(3, W.STOKES, 37, 70, seed=115)
+    b = W.small_cluster(4, W.STOKES, 50, 90, seed=116)
+    b.centre = b.centre + 100.0
+    Xa, tba = a.world_points("trg")
+    Ya, sba = a.world_points("src")
+    Xb, tbb = b.world_points("trg")
+    Yb, sbb = b.world_points("src")
+    X, Y = np.concatenate([Xa, Xb]), np.concatenate([Ya, Yb])
+    f = np.random.default_rng(117).standard_normal((Y.shape[0], 3))
+    sp = np.array([0, 3, 7], np.int64)
+    tp = np.concatenate([[0], np.cumsum([70] * 3 + [90] * 4)]).astype(np.int64)
+    pp = np.concatenate([[0], np.cumsum([37] * 3 + [50] * 4)]).astype(np.int64)
+    ref = np.concatenate([O.p2p_field(O.FIELD_PRESSURE, Xa, tba, Ya, sba, f[:len(Ya)]),
+                          O.p2p_field(O.FIELD_PRESSURE, Xb, tbb, Yb, sbb, f[len(Ya):])])
+    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 2e-5)):
+        p = mfs.p2p_stokes_pressure(sp, tp, pp, _dev(X), _dev(Y), _dev(f), 0, prec)
+        assert rel_inf(p.cpu().numpy(), ref) <= tol
+
+
+def test_translating_sphere_closed_forms():
+    """Resistance solve of one sphere moving with U, then (GPU) pressure
+    3 mu a U.x / (2 r^3) outside and surface traction -(3 mu / (2 a)) U."""
+    mfs = _mfs()
+    wl = W.single_sphere(W.STOKES)
+    U = np.array([1.0, 0.3, -0.2, 0.0, 0.0, 0.0])
+    plan = mfs.Plan.from_workload(wl, mfs.FP64, formulation=mfs.RESISTANCE)
+    F, info = plan.solve(_dev(U), tol=1e-12)
+    _, lam = plan.extract(info["gamma"], want_sigma=True)
+    Y = torch.tensor(wl.shapes[0].src, dtype=torch.float64, device="cuda")
+    dirs = _unit(60, 3)
+    sp, pp = [0, 1], [0, Y.shape[0]]
+    X = 1.5 * dirs
+    p = mfs.p2p_stokes_pressure(sp, [0, 60], pp, _dev(X), Y, lam.view(-1, 3), 0, mfs.FP64).cpu().numpy()
+    pex = 1.5 * (X @ U[:3]) / 1.5 ** 3
+    assert np.abs(p - pex).max() < 1e-4 * np.abs(pex).max()
+    T = mfs.p2p_stokes_traction(sp, [0, 60], pp, _dev(dirs), _dev(dirs), Y, lam.view(-1, 3), 0, mfs.FP64)
+    assert np.abs(T.cpu().numpy() + 1.5 * U[:3]).max() < 1e-2 * 1.5
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_surface_residual_matches_oracle(kind):
+    mfs = _mfs()
+    wl = W.small_cluster(4, kind, 60, 130, seed=118, axes=(1.0, 1.0, 1.0))
+    pr = O.Problem.from_workload(wl)
+    sol = pr.solve(wl.net[0], tol=1e-12)
+    test = W.fibonacci_sphere(500, 1.0)
+    ref = pr.surface_residual(sol["sigma"], sol["out"], test)
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 2e-6)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        eps = plan.surface_residual(_dev(sol["sigma"]), _dev(np.asarray(sol["out"]).reshape(-1)), test, prec=prec)
+        e = np.abs(eps.cpu().numpy() - ref).max()
+        print(kind, prec, "max eps", ref.max(), "abs diff", e)
+        assert e <= tol
+        # the GPU's own solve gives the same residual picture
+        out, info = plan.solve(_dev(net_flat(wl)), tol=1e-10)
+        _, sigma = plan.extract(info["gamma"], info["s0"], want_sigma=True)
+        eps2 = plan.surface_residual(sigma, out, test).cpu().numpy()
+        assert abs(eps2.max() - ref.max()) <= 1e-3 * ref.max() + tol
+        plan.close()
