@@ -19,7 +19,7 @@ over the stacked output.  Bars (the same as the per-entry-point tests):
   U or phi (solve)               1e-8      1e-5   the outputs the method reports
   dJ/dc (adjoint, Stokes)        1e-8      1e-5   J = sum |U|^2; FP64 tol 1e-12, mixed tol 1e-8
   resistance / capacitance (Section 2): rhs 1e-13 / 1e-13, S^+ apply and
-  A gamma as above, F or q from the solve 1e-8 / 1e-5
+  A gamma as above, F or q from the solve 1e-8 / 1e-5 (mixed solve at tol 1e-6)
 
 The oracle's solves run at tol 1e-12.
 """
@@ -158,7 +158,9 @@ def _rows(kind):
         add("res: rhs b", prec, rel_inf(_np(b), rb_ref))
         add("res: S^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), r_ref_p))
         add("res: A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), r_ref_A))
-        out, info = plan.solve(_dev(data), tol=1e-10 if prec == mfs.FP64 else 1e-5)
+        # the Dirichlet problems are worse conditioned (more iterations); their mixed bar is
+        # taken at tol 1e-6, as for the full-size solves
+        out, info = plan.solve(_dev(data), tol=1e-10 if prec == mfs.FP64 else 1e-6)
         assert info["status"] == mfs.MFS_OK
         add("res: F / q", prec, rel_inf(_np(out), r_sol["out"]))
         plan.close()
