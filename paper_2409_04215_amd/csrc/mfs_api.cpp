@@ -396,6 +396,10 @@ struct mfs_plan_s {
     // GMRES
     int gm_cap = 0;
     DevBuf V, Wv, R, X, dots_partial, dots, nrm, coef, chunks, sys_chunk_ptr, flag;
+    // pinned host staging of the per-iteration GMRES transfers (true asynchronous copies)
+    double *h_dots = nullptr;  // [n_sys * 2 * (gm_cap + 2)] CGS coefficients, then [n_sys] norms
+    double *h_scale = nullptr; // [n_sys]
+    int32_t *h_act = nullptr;  // [n_sys]
     // backward
     DevBuf bw_sigma, bw_glam, bw_g, bw_w, bw_gt, bw_gs;
     // optional timing of the matvec pair-sum kernel (per precision)
@@ -430,6 +434,14 @@ struct mfs_plan_s {
             for (auto &g : row)
                 if (g) (void)hipGraphExecDestroy(g);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        free_pinned();
+    }
+    void free_pinned() {
+        if (h_dots) (void)hipHostFree(h_dots);
+        if (h_scale) (void)hipHostFree(h_scale);
+        if (h_act) (void)hipHostFree(h_act);
+        h_dots = h_scale = nullptr;
+        h_act = nullptr;
     }
     std::vector<VecChunk> h_chunks;
     std::vector<int32_t> h_sys_chunk_ptr;
@@ -536,9 +548,11 @@ int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &g
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const GemmGroup &g = groups[gi];
         const int kchunk = (int)(((g.K + n_split - 1) / n_split + 63) / 64 * 64);
+        // column tiles innermost: the four waves of a workgroup (consecutive tiles) then hold
+        // the same rows and K range of A, which the CU fetches once for all of them
         for (int m0 = 0; m0 < g.M; m0 += 32)
-            for (int n0 = 0; n0 < g.ncol; n0 += 32)
-                for (int sp = 0; sp < n_split; ++sp) {
+            for (int sp = 0; sp < n_split; ++sp)
+                for (int n0 = 0; n0 < g.ncol; n0 += 32) {
                     const int k0 = std::min(g.K, sp * kchunk), k1 = std::min(g.K, k0 + kchunk);
                     tiles.push_back(GemmTile{(int32_t)gi, m0, n0, k0, k1, sp});
                 }
@@ -1263,6 +1277,15 @@ int ensure_krylov(mfs_plan p, int max_iter) {
     MFS_TRY(p->dots.reserve((size_t)S * 2 * (max_iter + 2) * sizeof(double)));
     MFS_TRY(p->nrm.reserve((size_t)S * sizeof(double)));
     MFS_TRY(p->coef.reserve((size_t)S * (max_iter + 2) * sizeof(double)));
+    // pinned staging (callers synchronise before a solve starts, so nothing is in flight here)
+    p->free_pinned();
+    const size_t nd = (size_t)S * 2 * (max_iter + 2) + S;
+    if (hipHostMalloc((void **)&p->h_dots, nd * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_scale, (size_t)S * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_act, (size_t)S * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        p->free_pinned();
+        return fail(MFS_ENOMEM, "hipHostMalloc of the GMRES staging buffers failed");
+    }
     p->gm_cap = max_iter;
     return MFS_OK;
 }
@@ -1275,9 +1298,11 @@ int sys_norms(mfs_plan p, const double *x, std::vector<double> &out, hipStream_t
     MFS_TRY(launch_reduce_sys((int)p->n_sys, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
                               p->nrm.as<double>(), 1, s));
     out.resize(p->n_sys);
-    MFS_HIP_TRY(hipMemcpyAsync(out.data(), p->nrm.ptr, p->n_sys * sizeof(double), hipMemcpyDeviceToHost, s));
+    double *h = p->h_dots;
+    MFS_HIP_TRY(hipMemcpyAsync(h, p->nrm.ptr, p->n_sys * sizeof(double), hipMemcpyDeviceToHost, s));
     MFS_HIP_TRY(hipStreamSynchronize(s));
-    for (auto &v : out) v = std::isnan(v) ? v : std::sqrt(std::max(0.0, v));  // keep NaN visible
+    for (int64_t i = 0; i < p->n_sys; ++i)
+        out[i] = std::isnan(h[i]) ? h[i] : std::sqrt(std::max(0.0, h[i]));  // keep NaN visible
     return MFS_OK;
 }
 
@@ -1342,9 +1367,11 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         n_act += act[sy];
     }
     if (n_act == 0) return MFS_OK;
-    std::vector<double> scale(S);
+    // host <-> device traffic of the loop goes through the plan's pinned buffers: the copies are
+    // asynchronous, and each buffer is rewritten only after the synchronisation that follows its copy
+    double *scale = p->h_scale;
     for (int sy = 0; sy < S; ++sy) scale[sy] = act[sy] ? 1.0 / beta[sy] : 0.0;
-    MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+    MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale, S * sizeof(double), hipMemcpyHostToDevice, s));
     MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), r, p->nrm.as<double>(), 1, V, s));
     // Hessenberg columns and Givens data per system
     std::vector<std::vector<double>> H(S, std::vector<double>((size_t)(max_iter + 1) * max_iter, 0.0));
@@ -1352,16 +1379,22 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         g(S, std::vector<double>(max_iter + 1, 0.0));
     std::vector<int> k(S, 0), live(act);
     for (int sy = 0; sy < S; ++sy) g[sy][0] = beta[sy];
-    std::vector<int32_t> act32(S);
-    std::vector<double> hbuf((size_t)S * 2 * ldh), nrm(S);
+    int32_t *act32 = p->h_act;
+    double *hbuf = p->h_dots, *nrm = p->h_dots + (size_t)S * 2 * ldh;
+    bool sent = false;  // the device mask equals live[] (it changes only when a system converges)
     for (int j = 0; j < max_iter; ++j) {
         int any = 0;
+        bool same = sent;
         for (int sy = 0; sy < S; ++sy) {
-            act32[sy] = live[sy];
+            same = same && act32[sy] == live[sy];
             any |= live[sy];
         }
         if (!any) break;
-        MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (!same) {
+            for (int sy = 0; sy < S; ++sy) act32[sy] = live[sy];
+            MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            sent = true;
+        }
         MFS_TRY(apply_A(p, A, V + (int64_t)j * n, w, prec, s));
         for (int sy = 0; sy < S; ++sy) counts[sy] += live[sy];
         // classical Gram-Schmidt, twice
@@ -1375,8 +1408,8 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), w, 0, 1, w, p->dots_partial.as<double>(), ldp, s));
         MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
                                   p->nrm.as<double>(), 1, s));
-        MFS_HIP_TRY(hipMemcpyAsync(hbuf.data(), dots, (size_t)S * 2 * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFS_HIP_TRY(hipMemcpyAsync(nrm.data(), p->nrm.ptr, S * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipMemcpyAsync(hbuf, dots, (size_t)S * 2 * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFS_HIP_TRY(hipMemcpyAsync(nrm, p->nrm.ptr, S * sizeof(double), hipMemcpyDeviceToHost, s));
         MFS_HIP_TRY(hipStreamSynchronize(s));
         for (int sy = 0; sy < S; ++sy) {
             scale[sy] = 0.0;
@@ -1424,7 +1457,7 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
             }
         }
         if (j + 1 < max_iter) {
-            MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+            MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale, S * sizeof(double), hipMemcpyHostToDevice, s));
             MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, p->nrm.as<double>(), 1, V + (int64_t)(j + 1) * n, s));
         }
     }
