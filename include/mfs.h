@@ -240,7 +240,8 @@ int mfs_matvec_adjoint(mfs_plan plan, const double *w, double *out, int prec, vo
 
 /* GMRES for A gamma = b (unrestarted per attempt, x0 = 0, classical
  * Gram-Schmidt with reorthogonalisation, Givens rotations on the host, FP64).
- * Every system stops on its own when ||r||_2 <= tol ||b||_2.  With a MIXED
+ * Every system stops on its own when ||r||_2 <= tol ||b||_2 (the iteration
+ * aims at tol/2, a margin for the outputs' error).  With a MIXED
  * plan the Krylov matvec is the mixed one; each attempt ends with an FP64
  * true-residual matvec, and systems above tol restart from their iterate on
  * that residual (iterative refinement, at most max_refine restarts).
@@ -309,9 +310,11 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * the matvec pair sum for candidate launch shapes (1 or 2 targets per lane x
  * 1024..16384 work items, which sets the source split x one workgroup per
  * item or a persistent grid of 2048 workgroups claiming items from a queue)
- * on `stream`, reps launches each, keeps the fastest for the forward and
- * transposed sums, and reports it ([host] outputs, may be NULL; *best_tpl is
- * negative for the persistent grid).  Synchronous. */
+ * on `stream`, reps launches each, and keeps for the forward and transposed
+ * sums the shape with the fewest source splits among those within 1.5% of the
+ * fastest (timing noise; fewer splits write fewer FP64 slices), reporting it
+ * ([host] outputs, may be NULL; *best_tpl is negative for the persistent
+ * grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
 /* Progress of long solves.  With a callback set, mfs_gmres_solve (and the
  * adjoint solve of mfs_solve_backward) calls it on the calling host thread

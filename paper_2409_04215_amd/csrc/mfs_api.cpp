@@ -1498,11 +1498,12 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     MFS_TRY(launch_fill(n, 0.0, x, s));
     double *r = p->R.as<double>();
     MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // mixed plans aim below tol: the FP64 check then passes without a restart
-    // (the GMRES estimate and the true FP64 residual agree to ~1e-7 relative),
-    // and the margin keeps the outputs within tol of the exact solution on
-    // the benchmark suspensions (at 0.8 one 10-body system ended at 1.1 tol)
-    const double inner = p->prec == MFS_MIXED ? 0.5 : 1.0;
+    // both precisions aim at half the tolerance: the relative residual bounds the
+    // outputs' error only up to the conditioning, and the margin keeps them within
+    // tol of the exact solution on the benchmark suspensions (at 0.8 one 10-body
+    // system ended at 1.1 tol); for mixed plans the FP64 check then also passes
+    // without a restart (the GMRES estimate and the true residual agree to ~1e-7)
+    const double inner = 0.5;
     for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
     int status = MFS_OK;
     if (p->prec == MFS_FP64) {
@@ -1691,6 +1692,8 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
     const int mis[5] = {1024, 2048, 4096, 8192, 16384};
     bool bper = false;
     int status = MFS_OK;
+    struct Cand { double ms; int n_split, tpl, mi, per; };
+    std::vector<Cand> timed;
     for (int per = 0; per < 2 && status >= 0; ++per) {
         for (int tpl : tpls) {
             for (int mi : mis) {
@@ -1716,12 +1719,7 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
                 MFS_HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
                 MFS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (ms / reps < best) {
-                    best = ms / reps;
-                    btpl = tpl;
-                    bmi = mi;
-                    bper = per != 0;
-                }
+                timed.push_back(Cand{ms / reps, std::max(cand.n_split, 1), tpl, mi, per});
             }
             if (status < 0) break;
         }
@@ -1729,6 +1727,20 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status < 0) return status;
+    // the fastest shape; among shapes within 1.5% of it (timing noise), the one with the fewest
+    // source splits (fewer FP64 slices written and re-read), then the fewest work items
+    for (const Cand &c : timed) best = std::min(best, c.ms);
+    const Cand *pick = nullptr;
+    for (const Cand &c : timed)
+        if (c.ms <= 1.015 * best &&
+            (!pick || c.n_split < pick->n_split || (c.n_split == pick->n_split && c.mi < pick->mi)))
+            pick = &c;
+    if (pick) {
+        btpl = pick->tpl;
+        bmi = pick->mi;
+        bper = pick->per != 0;
+        best = pick->ms;
+    }
     p->tuned_tpl = btpl;
     p->tuned_min_items = bmi;
     MFS_TRY(build_p2p_items(p->p2p_fwd, p->n_sys, p->sys_body_ptr.data(), trg_row.data(), src_row.data(),
