@@ -1491,8 +1491,10 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     MFS_TRY(sys_norms(p, b, bn, s));
     for (int sy = 0; sy < S; ++sy)
         if (!std::isfinite(bn[sy])) return fail(MFS_ENUMERIC, "non-finite right-hand side");
-    std::vector<double> target(S), est(S), rn(S);
+    std::vector<double> target(S), est(S), rn(S, 0.0);
     std::vector<int> counts(S, 0), active(S, 1), checks(S, 0);
+    for (int sy = 0; sy < S; ++sy)
+        if (bn[sy] == 0.0) active[sy] = 0;  // b = 0: gamma = 0 is exact, nothing to iterate or check
     p->prog_bnorm = bn;
     p->stop_requested = false;
     MFS_TRY(launch_fill(n, 0.0, x, s));
@@ -1514,6 +1516,7 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
         }
     } else {
         for (int attempt = 0; attempt <= max_refine; ++attempt) {
+            if (std::find(active.begin(), active.end(), 1) == active.end()) break;
             MFS_TRY(gmres_attempt(p, A, MFS_MIXED, r, x, target, max_iter, active, counts, est, s));
             // true residual in FP64
             std::vector<int32_t> act32(active.begin(), active.end());
