@@ -276,13 +276,14 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
                        int32_t *iters, double *relres, void *stream);
 /* (MFS_MOBILITY plans only; MFS_EUNSUPPORTED for MFS_RESISTANCE.) */
 
-/* Surface residual (eq. (residual)): eps(x) = |u(x) - g(x)| / |g(x)| at test
- * points on every body surface, with u the representation of the full
- * strengths sigma [device, lambda layout, e.g. from mfs_extract] over all
- * proxies of the system (same-body pairs included) and g the body's rigid
- * motion v + omega x (x - c) (Stokes) or its potential phi (Laplace) from
+/* Surface residual at test points on every body surface, with u the
+ * representation of the full strengths sigma [device, lambda layout, e.g. from
+ * mfs_extract] over all proxies of the system (same-body pairs included) and
  * motion [device, net layout: the solve's output, or the Dirichlet data of a
- * resistance solve].  Test points per shape in the shape frame:
+ * resistance solve].  Stokes (eq. (residual)): eps(x) = |u(x) - g(x)| / |g(x)|
+ * with g = v + omega x (x - c), the body's rigid motion.  Laplace: the
+ * absolute error eps(x) = |u(x) - phi| against the body's potential phi, the
+ * measure of the elastance convergence study (Sec. 6, Fig. f:elastconv(a)).  Test points per shape in the shape frame:
  * shape_n_test [host][n_shape], shape_test [host] concatenated, sum x 3.
  * eps [device] body by body; u_test [device, optional] receives u at the
  * points (3 or 1 values per point).  prec selects the pair arithmetic.

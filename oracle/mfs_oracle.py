@@ -479,10 +479,13 @@ class Problem:
 
     # -- surface residual (eq. (residual)) ------------------------------------------------
     def surface_residual(self, sigma: np.ndarray, out: np.ndarray, test_local) -> np.ndarray:
-        """eps_res(x) = |u(x) - g(x)| / |g(x)| at test points on every body
-        surface: u is the representation with the full strengths sigma over all
-        proxies (self included), g the body's rigid motion v + omega x (x - c)
-        (Stokes) or its potential (Laplace) from the solve's outputs.
+        """Surface residual at test points on every body surface, u being the
+        representation with the full strengths sigma over all proxies (self
+        included).  Stokes: eps_res(x) = |u(x) - g(x)| / |g(x)| with g the
+        body's rigid motion v + omega x (x - c) (eq. (residual)).  Laplace: the
+        absolute error |u(x) - phi_k| against the body's potential, the
+        quantity whose maximum the elastance convergence study plots (Sec. 6,
+        Fig. f:elastconv(a)).
         test_local: (n_t, 3) points on the surface of the shape, body frame
         (one shape for all bodies).  Returns eps stacked body by body."""
         pts, ids = [], []
@@ -495,7 +498,7 @@ class Problem:
         out = np.asarray(out, np.float64)
         if self.kind == LAPLACE:
             g = out[tb]
-            return np.abs(u - g) / np.abs(g)
+            return np.abs(u - g)
         c = np.stack([self.bodies[k].centre for k in tb])
         g = out[tb, :3] + np.cross(out[tb, 3:], Xt - c)
         return np.linalg.norm(u - g, axis=1) / np.linalg.norm(g, axis=1)

@@ -159,8 +159,10 @@ __global__ void field_reduce_kernel(int64_t n, const double *__restrict__ partia
     out[v] = s;
 }
 
-// eps(x) = |u(x) - g(x)| / |g(x)| per test point (eq. (residual)): g = v + omega x (x - c)
-// from the body's rigid motion (Stokes) or the body potential (Laplace).
+// Surface residual per test point.  Stokes: eps(x) = |u(x) - g(x)| / |g(x)| with g = v + omega x (x - c)
+// from the body's rigid motion (eq. (residual)).  Laplace: the absolute error |u(x) - phi_k| against the
+// body potential, the measure of the elastance convergence study (Sec. 6, Fig. f:elastconv(a)); a relative
+// one would divide by potentials that may be near zero.
 __global__ void residual_kernel(int64_t n, const int32_t *__restrict__ body, const int32_t *__restrict__ kind,
                                 const int64_t *__restrict__ net_off, const double *__restrict__ off64,
                                 const double *__restrict__ u, const int64_t *__restrict__ u_off,
@@ -171,7 +173,7 @@ __global__ void residual_kernel(int64_t n, const int32_t *__restrict__ body, con
     const double *m = motion + net_off[b];
     const double *ui = u + u_off[i];
     if (kind[b] == MFS_LAPLACE) {
-        eps[i] = fabs(ui[0] - m[0]) / fabs(m[0]);
+        eps[i] = fabs(ui[0] - m[0]);
         return;
     }
     const double *d = off64 + 4 * i;

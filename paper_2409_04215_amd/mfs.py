@@ -342,7 +342,8 @@ class Plan:
 
     def surface_residual(self, sigma: torch.Tensor, motion: torch.Tensor, test_points, prec: Optional[int] = None,
                          want_u: bool = False, stream=None):
-        """eps = |u - g| / |g| at test points on every body (see mfs_surface_residual).
+        """Surface residual at test points on every body (see mfs_surface_residual):
+        |u - g| / |g| for Stokes bodies, |u - phi| for Laplace bodies.
         test_points: one (n, 3) array in the shape frame per shape (or one array
         for a one-shape plan).  Returns eps [n_test_total] (and u if want_u)."""
         pts = [test_points] if not isinstance(test_points, (list, tuple)) else list(test_points)
