@@ -210,6 +210,17 @@ int mfs_plan_destroy(mfs_plan plan);
  * sigma_min/sigma_max over the plan's factors ([host] outputs, any may be NULL). */
 int mfs_plan_sizes(mfs_plan plan, int64_t *n_gamma, int64_t *n_lambda, int64_t *n_net,
                    double *min_sigma_ratio);
+/* Moves the plan's bodies: new centres [host][n_body][3] and rotations
+ * [host][n_body][3][3] (same layout as in the descriptor).  S_L, L, K_N and
+ * the completion depend only on points relative to their body, so the
+ * one-body factors stay (one factorisation per shape serves every congruent
+ * body, Sec. 3.3, Remark on congruent bodies); only the world offsets, Gram
+ * inverses and pair-operand positions are rebuilt, into the same device
+ * buffers (captured matvec graphs stay valid).  The plan then computes exactly
+ * what a new plan with these bodies computes.  MFS_EINVAL for NULL or
+ * non-finite input.  Synchronous; no work on the plan may be in flight on
+ * another stream. */
+int mfs_plan_set_bodies(mfs_plan plan, const double *centre, const double *rot, void *stream);
 
 /* Completion strengths and right-hand side (eqs. (al0), (erhsK); (lambda01),
  * (lambda02), (stou0)): s_0 = (q/N) 1 or K_N (K_N^T K_N)^{-1} [f; t] per body,

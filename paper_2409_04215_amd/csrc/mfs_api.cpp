@@ -367,6 +367,10 @@ struct mfs_plan_s {
     std::vector<int32_t> kind, n_src, n_trg, factor_of_body, shape_of_body;
     std::vector<double> rot_h;  // [n_body][9]
     int64_t n_shape = 0;
+    // shape point sets (shape frame) and per-shape proxy Gram inverses, kept so bodies can move
+    std::vector<double> shape_src_h, shape_trg_h, G0i_h;
+    std::vector<int64_t> sso, sto;
+    std::vector<char> G0_ok;
     std::vector<int64_t> gam_off, lam_off, net_off;  // n_body + 1 entries
     std::vector<int64_t> src_row, trg_row;           // n_body + 1 entries
     int64_t n_gamma = 0, n_lambda = 0, n_net = 0, n_srcp = 0, n_trgp = 0;
@@ -739,6 +743,80 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
 
 }  // namespace
 
+// Everything of a plan that depends on where the bodies are: centres, rotations,
+// world-axis offsets of every point (FP64 and FP32), per-body Gram inverses
+// G^-1 = R G0^-1 R^T, and the positions in the pair-operand records (strengths
+// are written per call).  The per-shape factors live in the shape frame and do
+// not depend on it (congruent bodies share one factorisation, Sec. 3.3).
+// Buffer sizes never change, so device pointers (and captured graphs) stay valid.
+static int upload_geometry(mfs_plan_s *p, const double *centre, const double *rot, hipStream_t s) {
+    const int64_t nb = p->n_body;
+    std::vector<double> so64(4 * p->n_srcp), to64(4 * p->n_trgp);
+    std::vector<float> so32(4 * p->n_srcp), to32(4 * p->n_trgp);
+    std::vector<double> gram(36 * nb, 0.0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int sh = p->shape_of_body[b];
+        const double *R = rot + 9 * b;
+        auto emit = [&](const double *loc, int n, int64_t row0, std::vector<double> &o64, std::vector<float> &o32) {
+            for (int i = 0; i < n; ++i) {
+                const double *q = loc + 3 * i;
+                for (int a = 0; a < 3; ++a) {
+                    const double v = R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2];
+                    o64[4 * (row0 + i) + a] = v;
+                    o32[4 * (row0 + i) + a] = (float)v;
+                }
+                o64[4 * (row0 + i) + 3] = 0.0;
+                o32[4 * (row0 + i) + 3] = 0.f;
+            }
+        };
+        emit(p->shape_src_h.data() + 3 * p->sso[sh], p->n_src[b], p->src_row[b], so64, so32);
+        emit(p->shape_trg_h.data() + 3 * p->sto[sh], p->n_trg[b], p->trg_row[b], to64, to32);
+        if (p->kind[b] == MFS_STOKES) {
+            if (!p->G0_ok[sh]) {
+                double G[36];
+                gram6(p->shape_src_h.data() + 3 * p->sso[sh], p->n_src[b], G);
+                if (!inv6(G, &p->G0i_h[36 * sh])) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
+                p->G0_ok[sh] = 1;
+            }
+            rotate_gram(&p->G0i_h[36 * sh], R, &gram[36 * b]);
+        }
+    }
+    p->rot_h.assign(rot, rot + 9 * nb);
+    std::vector<double> cen(centre, centre + 3 * nb), rotv(rot, rot + 9 * nb);
+    MFS_TRY(upload_vec(p->d_rot, rotv, s));
+    MFS_TRY(upload_vec(p->d_gram_inv, gram, s));
+    MFS_TRY(upload_vec(p->d_centre, cen, s));
+    MFS_TRY(upload_vec(p->d_src_off64, so64, s));
+    MFS_TRY(upload_vec(p->d_trg_off64, to64, s));
+    MFS_TRY(upload_vec(p->d_src_off32, so32, s));
+    MFS_TRY(upload_vec(p->d_trg_off32, to32, s));
+    // pair operand records: positions now, strengths written per call
+    auto records = [&](int64_t n, const std::vector<double> &o64, const std::vector<float> &o32, DevBuf &S32,
+                       DevBuf &L32, DevBuf &S64, DevBuf &L64) -> int {
+        std::vector<SrcS32> s32(n);
+        std::vector<SrcL32> l32(n);
+        std::vector<SrcS64> s64(n);
+        std::vector<SrcL64> l64(n);
+        for (int64_t j = 0; j < n; ++j) {
+            s32[j].pos = make_float4(o32[4 * j], o32[4 * j + 1], o32[4 * j + 2], 0.f);
+            s32[j].str = make_float4(0.f, 0.f, 0.f, 0.f);
+            l32[j] = make_float4(o32[4 * j], o32[4 * j + 1], o32[4 * j + 2], 0.f);
+            s64[j] = SrcS64{{o64[4 * j], o64[4 * j + 1], o64[4 * j + 2], 0.0}, {0.0, 0.0, 0.0, 0.0}};
+            l64[j] = SrcL64{{o64[4 * j], o64[4 * j + 1], o64[4 * j + 2], 0.0}};
+        }
+        MFS_TRY(upload_vec(S32, s32, s));
+        MFS_TRY(upload_vec(L32, l32, s));
+        MFS_TRY(upload_vec(S64, s64, s));
+        MFS_TRY(upload_vec(L64, l64, s));
+        // the staging vectors are pageable and local: finish the copies before they go
+        MFS_HIP_TRY(hipStreamSynchronize(s));
+        return MFS_OK;
+    };
+    MFS_TRY(records(p->n_srcp, so64, so32, p->fS32, p->fL32, p->fS64, p->fL64));
+    MFS_TRY(records(p->n_trgp, to64, to32, p->tS32, p->tL32, p->tS64, p->tL64));
+    return MFS_OK;
+}
+
 extern "C" {
 
 const char *mfs_last_error(void) { return g_last_error.c_str(); }
@@ -842,7 +920,6 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     p->formulation = d->formulation;
     p->n_shape = d->n_shape;
     p->shape_of_body.assign(d->shape_of_body, d->shape_of_body + nb);
-    p->rot_h.assign(d->rot, d->rot + 9 * nb);
     p->mu = d->mu;
     p->n_sys = d->n_sys;
     p->n_body = nb;
@@ -895,44 +972,19 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
         F.dM = dim * d->shape_n_trg[F.shape];
         p->factors.push_back(F);
     }
-    // host geometry: world-axis offsets of every point, Gram inverses per body
-    std::vector<double> so64(4 * p->n_srcp), to64(4 * p->n_trgp);
-    std::vector<float> so32(4 * p->n_srcp), to32(4 * p->n_trgp);
-    std::vector<double> gram(36 * nb, 0.0);
+    // shape point sets are kept: bodies may move later (mfs_plan_set_bodies)
+    p->sso = sso;
+    p->sto = sto;
+    p->shape_src_h.assign(d->shape_src, d->shape_src + 3 * sso[d->n_shape]);
+    p->shape_trg_h.assign(d->shape_trg, d->shape_trg + 3 * sto[d->n_shape]);
+    p->G0i_h.assign(36 * d->n_shape, 0.0);
+    p->G0_ok.assign(d->n_shape, 0);
     std::vector<int32_t> sbody(p->n_srcp), tbody(p->n_trgp);
-    std::vector<double> G0i_cache(36 * d->n_shape, 0.0);
-    std::vector<char> G0_ok(d->n_shape, 0);
     for (int64_t b = 0; b < nb; ++b) {
-        const int sh = d->shape_of_body[b];
-        const double *R = d->rot + 9 * b;
-        auto emit = [&](const double *loc, int n, int64_t row0, std::vector<double> &o64, std::vector<float> &o32,
-                        std::vector<int32_t> &ids) {
-            for (int i = 0; i < n; ++i) {
-                const double *q = loc + 3 * i;
-                for (int a = 0; a < 3; ++a) {
-                    const double v = R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2];
-                    o64[4 * (row0 + i) + a] = v;
-                    o32[4 * (row0 + i) + a] = (float)v;
-                }
-                o64[4 * (row0 + i) + 3] = 0.0;
-                o32[4 * (row0 + i) + 3] = 0.f;
-                ids[row0 + i] = (int32_t)b;
-            }
-        };
-        emit(d->shape_src + 3 * sso[sh], p->n_src[b], p->src_row[b], so64, so32, sbody);
-        emit(d->shape_trg + 3 * sto[sh], p->n_trg[b], p->trg_row[b], to64, to32, tbody);
-        if (p->kind[b] == MFS_STOKES) {
-            if (!G0_ok[sh]) {
-                double G[36];
-                gram6(d->shape_src + 3 * sso[sh], p->n_src[b], G);
-                if (!inv6(G, &G0i_cache[36 * sh])) return fail(MFS_ENUMERIC, "singular proxy Gram matrix");
-                G0_ok[sh] = 1;
-            }
-            rotate_gram(&G0i_cache[36 * sh], R, &gram[36 * b]);
-        }
+        std::fill(sbody.begin() + p->src_row[b], sbody.begin() + p->src_row[b + 1], (int32_t)b);
+        std::fill(tbody.begin() + p->trg_row[b], tbody.begin() + p->trg_row[b + 1], (int32_t)b);
     }
     std::vector<int32_t> src_row32(p->src_row.begin(), p->src_row.end()), trg_row32(p->trg_row.begin(), p->trg_row.end());
-    std::vector<double> cen(d->centre, d->centre + 3 * nb), rot(d->rot, d->rot + 9 * nb);
     MFS_TRY(upload_vec(p->d_kind, p->kind, s));
     MFS_TRY(upload_vec(p->d_nsrc, p->n_src, s));
     MFS_TRY(upload_vec(p->d_ntrg, p->n_trg, s));
@@ -941,48 +993,9 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     MFS_TRY(upload_vec(p->d_net_off, p->net_off, s));
     MFS_TRY(upload_vec(p->d_src_row32, src_row32, s));
     MFS_TRY(upload_vec(p->d_trg_row32, trg_row32, s));
-    MFS_TRY(upload_vec(p->d_rot, rot, s));
-    MFS_TRY(upload_vec(p->d_gram_inv, gram, s));
-    MFS_TRY(upload_vec(p->d_centre, cen, s));
-    MFS_TRY(upload_vec(p->d_src_off64, so64, s));
-    MFS_TRY(upload_vec(p->d_trg_off64, to64, s));
-    MFS_TRY(upload_vec(p->d_src_off32, so32, s));
-    MFS_TRY(upload_vec(p->d_trg_off32, to32, s));
     MFS_TRY(upload_vec(p->d_src_body, sbody, s));
     MFS_TRY(upload_vec(p->d_trg_body, tbody, s));
-    // pair operand records: positions now, strengths written per call
-    {
-        std::vector<SrcS32> fs32(p->n_srcp);
-        std::vector<SrcL32> fl32(p->n_srcp);
-        std::vector<SrcS64> fs64(p->n_srcp);
-        std::vector<SrcL64> fl64(p->n_srcp);
-        for (int64_t j = 0; j < p->n_srcp; ++j) {
-            fs32[j].pos = make_float4(so32[4 * j], so32[4 * j + 1], so32[4 * j + 2], 0.f);
-            fs32[j].str = make_float4(0.f, 0.f, 0.f, 0.f);
-            fl32[j] = make_float4(so32[4 * j], so32[4 * j + 1], so32[4 * j + 2], 0.f);
-            fs64[j] = SrcS64{{so64[4 * j], so64[4 * j + 1], so64[4 * j + 2], 0.0}, {0.0, 0.0, 0.0, 0.0}};
-            fl64[j] = SrcL64{{so64[4 * j], so64[4 * j + 1], so64[4 * j + 2], 0.0}};
-        }
-        MFS_TRY(upload_vec(p->fS32, fs32, s));
-        MFS_TRY(upload_vec(p->fL32, fl32, s));
-        MFS_TRY(upload_vec(p->fS64, fs64, s));
-        MFS_TRY(upload_vec(p->fL64, fl64, s));
-        std::vector<SrcS32> ts32(p->n_trgp);
-        std::vector<SrcL32> tl32(p->n_trgp);
-        std::vector<SrcS64> ts64(p->n_trgp);
-        std::vector<SrcL64> tl64(p->n_trgp);
-        for (int64_t j = 0; j < p->n_trgp; ++j) {
-            ts32[j].pos = make_float4(to32[4 * j], to32[4 * j + 1], to32[4 * j + 2], 0.f);
-            ts32[j].str = make_float4(0.f, 0.f, 0.f, 0.f);
-            tl32[j] = make_float4(to32[4 * j], to32[4 * j + 1], to32[4 * j + 2], 0.f);
-            ts64[j] = SrcS64{{to64[4 * j], to64[4 * j + 1], to64[4 * j + 2], 0.0}, {0.0, 0.0, 0.0, 0.0}};
-            tl64[j] = SrcL64{{to64[4 * j], to64[4 * j + 1], to64[4 * j + 2], 0.0}};
-        }
-        MFS_TRY(upload_vec(p->tS32, ts32, s));
-        MFS_TRY(upload_vec(p->tL32, tl32, s));
-        MFS_TRY(upload_vec(p->tS64, ts64, s));
-        MFS_TRY(upload_vec(p->tL64, tl64, s));
-    }
+    MFS_TRY(upload_geometry(p.get(), d->centre, d->rot, s));
     // pair-sum items, forward (targets = collocation points) and transposed (targets = proxies)
     {
         std::vector<int64_t> src_row(p->src_row), trg_row(p->trg_row);
@@ -1042,6 +1055,20 @@ int mfs_plan_sizes(mfs_plan p, int64_t *n_gamma, int64_t *n_lambda, int64_t *n_n
     if (n_lambda) *n_lambda = p->n_lambda;
     if (n_net) *n_net = p->n_net;
     if (min_sigma_ratio) *min_sigma_ratio = p->min_ratio;
+    return MFS_OK;
+}
+
+int mfs_plan_set_bodies(mfs_plan p, const double *centre, const double *rot, void *stream) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (!centre || !rot) return fail(MFS_EINVAL, "NULL body arrays");
+    for (int64_t q = 0; q < 3 * p->n_body; ++q)
+        if (!std::isfinite(centre[q])) return fail(MFS_EINVAL, "non-finite centre");
+    for (int64_t q = 0; q < 9 * p->n_body; ++q)
+        if (!std::isfinite(rot[q])) return fail(MFS_EINVAL, "non-finite rotation");
+    hipStream_t s = (hipStream_t)stream;
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    MFS_TRY(upload_geometry(p, centre, rot, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
     return MFS_OK;
 }
 

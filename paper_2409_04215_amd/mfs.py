@@ -68,6 +68,7 @@ def lib():
         L.mfs_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(PlanDesc), _vp]
         L.mfs_plan_destroy.argtypes = [_vp]
         L.mfs_plan_sizes.argtypes = [_vp, _i64p, _i64p, _i64p, _dp]
+        L.mfs_plan_set_bodies.argtypes = [_vp, _dp, _dp, _vp]
         L.mfs_rhs.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.mfs_precond_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_matvec.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
@@ -272,6 +273,18 @@ class Plan:
         return cls(precision, wl.sys_body_ptr, wl.sys_kind, wl.centre, wl.rot, wl.shape_of_body,
                    [s.src for s in wl.shapes], [s.trg for s in wl.shapes], mu=wl.mu, device=device, stream=stream,
                    formulation=formulation)
+
+    def set_bodies(self, centre, rot, stream=None):
+        """Moves the bodies (new centres [n_body, 3] and rotations [n_body, 3, 3]);
+        the one-body factors are kept (see mfs_plan_set_bodies)."""
+        c = np.ascontiguousarray(np.asarray(centre, dtype=np.float64).reshape(-1, 3))
+        r = np.ascontiguousarray(np.asarray(rot, dtype=np.float64).reshape(-1, 3, 3))
+        if c.shape[0] != len(self.shape_of_body) or r.shape[0] != len(self.shape_of_body):
+            raise ValueError("set_bodies: one centre and one rotation per body")
+        with torch.cuda.device(self.device):
+            _check(lib().mfs_plan_set_bodies(self._h, c.ctypes.data_as(_dp), r.ctypes.data_as(_dp), _stream(stream)),
+                   "mfs_plan_set_bodies")
+        self.centre, self.rot = c, r
 
     def close(self):
         if self._h:

@@ -1,0 +1,139 @@
+"""Moving the bodies of a resident plan (mfs_plan_set_bodies).
+
+S_L, L, K_N and the completion depend only on points relative to their body,
+so one factorisation per shape serves every congruent body wherever it sits
+(Sec. 3.3).  A plan whose bodies are moved must therefore compute exactly what
+a new plan built at the new positions computes: the matvec and the whole solve
+agree bit for bit (same kernels, same data, fixed reduction orders), also when
+the matvec is replayed from a graph captured before the move, and they match
+the oracle at the new positions to the usual parity bars.
+
+A step of length h along the unit descent direction -g/|g|, g = dJ/dc, taken
+by moving the bodies, lowers the loss J = sum_k |U^(k)|^2 by the first-order
+amount: J(c - h g/|g|) = J - h|g| + O(h^2) (Taylor).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import net_flat, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+def _pair(kind, n_body, seed):
+    """Two clusters of the same shapes (same point sets), different centres and rotations."""
+    a = W.small_cluster(n_body, kind, 45, 130, seed=seed)
+    b = W.small_cluster(n_body, kind, 45, 130, seed=seed + 1)
+    assert np.array_equal(a.shapes[0].src, b.shapes[0].src) and np.array_equal(a.shapes[0].trg, b.shapes[0].trg)
+    assert not np.allclose(a.centre, b.centre)
+    return a, b
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_moved_plan_equals_new_plan(kind):
+    mfs = _mfs()
+    a, b = _pair(kind, 5, 141)
+    pr_b = O.Problem.from_workload(b)
+    g = W.random_vector(pr_b.n_gamma, 142)
+    ref_mv = pr_b.matvec(g)
+    ref_out = pr_b.solve(b.net[0], tol=1e-12)["out"]
+    for prec, tol_mv, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-4, 1e-6)):
+        moved = mfs.Plan.from_workload(a, prec)
+        moved.solve(_dev(net_flat(a)), tol=1e-8)  # used at the old positions first
+        moved.set_bodies(b.centre, b.rot)
+        fresh = mfs.Plan.from_workload(b, prec)
+        for p in (mfs.FP64, mfs.MIXED):
+            assert torch.equal(moved.matvec(_dev(g), p), fresh.matvec(_dev(g), p))
+            assert torch.equal(moved.matvec_adjoint(_dev(g), p), fresh.matvec_adjoint(_dev(g), p))
+        assert rel_inf(moved.matvec(_dev(g), prec).cpu().numpy(), ref_mv) <= tol_mv
+        out_m, info_m = moved.solve(_dev(net_flat(b)), tol=1e-10)
+        out_f, info_f = fresh.solve(_dev(net_flat(b)), tol=1e-10)
+        assert info_m["status"] == mfs.MFS_OK
+        assert torch.equal(out_m, out_f) and list(info_m["iters"]) == list(info_f["iters"])
+        assert rel_inf(out_m.cpu().numpy(), ref_out) <= bar
+        moved.close()
+        fresh.close()
+
+
+def test_moved_plan_graph_replay_and_bodies_of_several_shapes():
+    """Three shapes mixed in one system; the matvec graph is captured at the
+    old positions and replayed after the move."""
+    mfs = _mfs()
+    shapes = [W.spheroid_shape(1.0, 2.0, 45, 130), W.spheroid_shape(1.0, 2.0, 70, 150),
+              W.spheroid_shape(1.0, 2.0, 33, 97)]
+    a, b = _pair(W.STOKES, 6, 143)
+    for wl in (a, b):
+        wl.shapes = shapes
+        wl.shape_of_body = np.array([0, 1, 2, 1, 0, 2], np.int32)
+    ref = O.Problem.from_workload(b).solve(b.net[0], tol=1e-12)["out"]
+    moved = mfs.Plan.from_workload(a, mfs.MIXED)
+    moved.set_graph(True)
+    moved.solve(_dev(net_flat(a)), tol=1e-8)  # captures the matvec graph at the old positions
+    moved.set_bodies(b.centre, b.rot)
+    fresh = mfs.Plan.from_workload(b, mfs.MIXED)
+    for _ in range(2):
+        out_m, info_m = moved.solve(_dev(net_flat(b)), tol=1e-8)
+        torch.cuda.synchronize()
+        out_f, _ = fresh.solve(_dev(net_flat(b)), tol=1e-8)
+        assert info_m["status"] == mfs.MFS_OK
+        assert torch.equal(out_m, out_f)
+        assert rel_inf(out_m.cpu().numpy(), ref) <= 1e-6
+    moved.close()
+    fresh.close()
+
+
+def test_set_bodies_rejects_bad_input_and_keeps_the_plan():
+    mfs = _mfs()
+    a, b = _pair(W.STOKES, 3, 145)
+    plan = mfs.Plan.from_workload(a, mfs.FP64)
+    g = _dev(W.random_vector(plan.n_gamma, 146))
+    before = plan.matvec(g, mfs.FP64)
+    bad = b.centre.copy()
+    bad[1, 2] = np.nan
+    with pytest.raises(RuntimeError):
+        plan.set_bodies(bad, b.rot)
+    with pytest.raises(ValueError):
+        plan.set_bodies(b.centre[:2], b.rot[:2])
+    assert torch.equal(plan.matvec(g, mfs.FP64), before)
+    plan.close()
+
+
+def test_gradient_step_by_moving_bodies():
+    """J(c - h g/|g|) = J - h |g| + O(h^2): one descent step through set_bodies."""
+    mfs = _mfs()
+    wl = W.small_cluster(4, W.STOKES, 60, 130, seed=147, axes=(1.0, 1.0, 1.0))
+    plan = mfs.Plan.from_workload(wl, mfs.FP64)
+    net = _dev(net_flat(wl))
+
+    def loss_and_grad():
+        out, info = plan.solve(net, tol=1e-12)
+        g, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=1e-12)
+        assert st == mfs.MFS_OK
+        return float((out * out).sum()), g.cpu().numpy()
+
+    J0, g0 = loss_and_grad()
+    gn = np.linalg.norm(g0)
+    c0 = wl.centre.copy()
+    for h in (2e-3, 1e-3):
+        plan.set_bodies(c0 - h * g0 / gn, wl.rot)
+        J1, _ = loss_and_grad()
+        pred = J0 - h * gn
+        print("h", h, "J0", J0, "J1", J1, "first-order", pred)
+        assert J1 < J0
+        assert abs(J1 - pred) <= 5.0 * h * h * gn + 1e-10 * J0  # the oracle gives 1.44 h^2 |g| here
+    plan.set_bodies(c0, wl.rot)
+    J_back, g_back = loss_and_grad()
+    assert J_back == J0 and np.array_equal(g_back, g0)
+    plan.close()
