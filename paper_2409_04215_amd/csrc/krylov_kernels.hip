@@ -103,6 +103,97 @@ __global__ void finite_kernel(int64_t n, const double *__restrict__ x, int32_t *
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// ---------------------------------------------------------------------------
+// GMRES least squares on the device, one thread per system
+// ---------------------------------------------------------------------------
+__global__ void givens_init_kernel(GivensState st) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= st.n_sys) return;
+    const double b = st.beta[sy];
+    st.g[(int64_t)sy * (st.cap + 1)] = b;
+    st.k[sy] = 0;
+    st.est[sy] = b;
+    st.scale[sy] = st.live[sy] ? 1.0 / b : 0.0;
+}
+
+// Column j of system sy (see givens_step_kernel); returns the status flags.
+__device__ int givens_column(const GivensState &st, int j, int sy) {
+    st.scale[sy] = 0.0;
+    if (!st.live[sy]) return 0;
+    const double *__restrict__ d0 = st.dots + (int64_t)sy * 2 * st.ldh;
+    const double *__restrict__ d1 = d0 + st.ldh;
+    const double *__restrict__ cs = st.cs + (int64_t)sy * st.cap;
+    const double *__restrict__ sn = st.sn + (int64_t)sy * st.cap;
+    double *__restrict__ Rj = st.R + (int64_t)sy * ((int64_t)st.cap * (st.cap + 1) / 2) + (int64_t)j * (j + 1) / 2;
+    double *__restrict__ g = st.g + (int64_t)sy * (st.cap + 1);
+    const double n2 = st.nrm2[sy];
+    const double hn = isnan(n2) ? n2 : sqrt(fmax(0.0, n2));
+    if (!isfinite(hn)) {
+        st.live[sy] = 0;
+        return 2;
+    }
+    double hi = d0[0] + d1[0];  // h_i as rotated so far
+    for (int i = 0; i < j; ++i) {
+        const double hnext = d0[i + 1] + d1[i + 1];
+        Rj[i] = cs[i] * hi + sn[i] * hnext;
+        hi = -sn[i] * hi + cs[i] * hnext;
+    }
+    const double rho = hypot(hi, hn);
+    if (!(rho > 0.0)) {
+        Rj[j] = 0.0;
+        st.k[sy] = j;
+        st.live[sy] = 0;
+        return 0;
+    }
+    const double c = hi / rho, s = hn / rho;
+    st.cs[(int64_t)sy * st.cap + j] = c;
+    st.sn[(int64_t)sy * st.cap + j] = s;
+    Rj[j] = rho;
+    const double gj = g[j];
+    g[j + 1] = -s * gj;
+    g[j] = c * gj;
+    st.k[sy] = j + 1;
+    const double e = fabs(g[j + 1]);
+    st.est[sy] = e;
+    const bool go_on = !(e <= st.target[sy] || hn == 0.0);
+    st.live[sy] = go_on;
+    if (go_on) st.scale[sy] = 1.0 / hn;
+    return go_on ? 1 : 0;
+}
+
+// Iteration j: column j of the Hessenberg matrix is h_i = (both CGS passes' coefficients)
+// for i <= j and h_{j+1} = |w|.  The earlier rotations act on it in order, a new rotation
+// zeroes h_{j+1}, and the rotated right-hand side g gives the residual estimate |g_{j+1}|.
+// A system stops when that estimate reaches its target, when h_{j+1} = 0 (the Krylov space
+// holds the solution), or at an exact breakdown (rho = 0: the solution lies in the first
+// j columns).  A non-finite column stops the system and flags it.  Every system's estimate
+// and flags go to the status block of the iteration.
+__global__ void givens_step_kernel(GivensState st, int j, double *__restrict__ status_est,
+                                   int32_t *__restrict__ status_flag) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= st.n_sys) return;
+    const int flag = givens_column(st, j, sy);
+    status_est[sy] = st.est[sy];
+    status_flag[sy] = flag;
+}
+
+// y = R^-1 g over the first k columns (back substitution); coef[sy][i] = y_i for i < k,
+// 0 for k <= i < nvec.
+__global__ void givens_solve_kernel(GivensState st, double *__restrict__ coef, int ld_coef, int nvec) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= st.n_sys) return;
+    const int kk = st.k[sy];
+    const double *__restrict__ R = st.R + (int64_t)sy * ((int64_t)st.cap * (st.cap + 1) / 2);
+    const double *__restrict__ g = st.g + (int64_t)sy * (st.cap + 1);
+    double *__restrict__ y = coef + (int64_t)sy * ld_coef;
+    for (int i = kk; i < nvec; ++i) y[i] = 0.0;
+    for (int i = kk - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < kk; ++c) t -= R[(int64_t)c * (c + 1) / 2 + i] * y[c];
+        y[i] = t / R[(int64_t)i * (i + 1) / 2 + i];
+    }
+}
+
 }  // namespace
 
 int launch_multi_dot(int n_chunk, const VecChunk *chunks, const double *V, int64_t ldv, int nvec, const double *w,
@@ -154,6 +245,29 @@ int launch_add_inplace(int64_t n, const double *a, double *out, hipStream_t s) {
 int launch_fill(int64_t n, double v, double *out, hipStream_t s) {
     if (n == 0) return MFS_OK;
     fill_kernel<<<nblk(n), 256, 0, s>>>(n, v, out);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_givens_init(const GivensState &st, hipStream_t s) {
+    if (st.n_sys == 0) return MFS_OK;
+    givens_init_kernel<<<(unsigned)((st.n_sys + 63) / 64), 64, 0, s>>>(st);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_givens_step(const GivensState &st, int j, double *status_est, int32_t *status_flag, hipStream_t s) {
+    if (st.n_sys == 0) return MFS_OK;
+    if (j < 0 || j >= st.cap) return fail(MFS_EINVAL, "internal: GMRES step beyond the Krylov capacity");
+    givens_step_kernel<<<(unsigned)((st.n_sys + 63) / 64), 64, 0, s>>>(st, j, status_est, status_flag);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_givens_solve(const GivensState &st, double *coef, int ld_coef, int nvec, hipStream_t s) {
+    if (st.n_sys == 0) return MFS_OK;
+    if (nvec > ld_coef || nvec > st.cap) return fail(MFS_EINVAL, "internal: GMRES solve beyond the Krylov capacity");
+    givens_solve_kernel<<<(unsigned)((st.n_sys + 63) / 64), 64, 0, s>>>(st, coef, ld_coef, nvec);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -400,10 +400,19 @@ struct mfs_plan_s {
     // GMRES
     int gm_cap = 0;
     DevBuf V, Wv, R, X, dots_partial, dots, nrm, coef, chunks, sys_chunk_ptr, flag;
-    // pinned host staging of the per-iteration GMRES transfers (true asynchronous copies)
-    double *h_dots = nullptr;  // [n_sys * 2 * (gm_cap + 2)] CGS coefficients, then [n_sys] norms
-    double *h_scale = nullptr; // [n_sys]
+    // least-squares state on the device (GivensState)
+    DevBuf gvR, gvCS, gvSN, gvG, gvK, gvScale, gvInit, gvEst;
+    // pinned host staging of the GMRES transfers (true asynchronous copies)
+    double *h_dots = nullptr;  // [n_sys] per-system norms
+    double *h_init = nullptr;  // [2 n_sys] residual targets, initial residual norms
     int32_t *h_act = nullptr;  // [n_sys]
+    // [STAT_SLOTS][stat_bytes()] status blocks of recent iterations, written by the device
+    // (fine-grained, mapped: d_stat is its device address)
+    char *h_stat = nullptr, *d_stat = nullptr;
+    static constexpr int STAT_SLOTS = 3;
+    hipEvent_t stat_ev[STAT_SLOTS] = {nullptr, nullptr, nullptr};
+    // est doubles, then flag int32, padded so every ring slot starts 16-byte aligned
+    size_t stat_bytes() const { return ((size_t)n_sys * 12 + 15) & ~(size_t)15; }
     // backward
     DevBuf bw_sigma, bw_glam, bw_g, bw_w, bw_gt, bw_gs;
     // optional timing of the matvec pair-sum kernel (per precision)
@@ -438,14 +447,37 @@ struct mfs_plan_s {
             for (auto &g : row)
                 if (g) (void)hipGraphExecDestroy(g);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        for (auto &e : stat_ev)
+            if (e) (void)hipEventDestroy(e);
         free_pinned();
     }
     void free_pinned() {
         if (h_dots) (void)hipHostFree(h_dots);
-        if (h_scale) (void)hipHostFree(h_scale);
+        if (h_init) (void)hipHostFree(h_init);
         if (h_act) (void)hipHostFree(h_act);
-        h_dots = h_scale = nullptr;
+        if (h_stat) (void)hipHostFree(h_stat);
+        h_dots = h_init = nullptr;
         h_act = nullptr;
+        h_stat = d_stat = nullptr;
+    }
+    GivensState givens() const {
+        GivensState st;
+        st.n_sys = (int)n_sys;
+        st.cap = gm_cap;
+        st.ldh = gm_cap + 2;
+        st.dots = dots.as<double>();
+        st.nrm2 = nrm.as<double>();
+        st.target = gvInit.as<double>();
+        st.beta = gvInit.as<double>() + n_sys;
+        st.R = gvR.as<double>();
+        st.cs = gvCS.as<double>();
+        st.sn = gvSN.as<double>();
+        st.g = gvG.as<double>();
+        st.k = gvK.as<int32_t>();
+        st.live = sys_active.as<int32_t>();
+        st.scale = gvScale.as<double>();
+        st.est = gvEst.as<double>();
+        return st;
     }
     std::vector<VecChunk> h_chunks;
     std::vector<int32_t> h_sys_chunk_ptr;
@@ -1304,14 +1336,29 @@ int ensure_krylov(mfs_plan p, int max_iter) {
     MFS_TRY(p->dots.reserve((size_t)S * 2 * (max_iter + 2) * sizeof(double)));
     MFS_TRY(p->nrm.reserve((size_t)S * sizeof(double)));
     MFS_TRY(p->coef.reserve((size_t)S * (max_iter + 2) * sizeof(double)));
+    MFS_TRY(p->gvR.reserve((size_t)S * ((size_t)max_iter * (max_iter + 1) / 2) * sizeof(double)));
+    MFS_TRY(p->gvCS.reserve((size_t)S * max_iter * sizeof(double)));
+    MFS_TRY(p->gvSN.reserve((size_t)S * max_iter * sizeof(double)));
+    MFS_TRY(p->gvG.reserve((size_t)S * (max_iter + 1) * sizeof(double)));
+    MFS_TRY(p->gvK.reserve((size_t)S * sizeof(int32_t)));
+    MFS_TRY(p->gvScale.reserve((size_t)S * sizeof(double)));
+    MFS_TRY(p->gvInit.reserve((size_t)S * 2 * sizeof(double)));
+    MFS_TRY(p->gvEst.reserve((size_t)S * sizeof(double)));
+    for (auto &e : p->stat_ev)
+        if (!e) MFS_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // pinned staging (callers synchronise before a solve starts, so nothing is in flight here)
     p->free_pinned();
-    const size_t nd = (size_t)S * 2 * (max_iter + 2) + S;
-    if (hipHostMalloc((void **)&p->h_dots, nd * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&p->h_scale, (size_t)S * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&p->h_act, (size_t)S * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&p->h_dots, (size_t)S * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_init, (size_t)S * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_act, (size_t)S * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_stat, p->STAT_SLOTS * p->stat_bytes(),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         p->free_pinned();
         return fail(MFS_ENOMEM, "hipHostMalloc of the GMRES staging buffers failed");
+    }
+    if (hipHostGetDevicePointer((void **)&p->d_stat, p->h_stat, 0) != hipSuccess) {
+        p->free_pinned();
+        return fail(MFS_EHIP, "hipHostGetDevicePointer of the GMRES status blocks failed");
     }
     p->gm_cap = max_iter;
     return MFS_OK;
@@ -1373,6 +1420,14 @@ int apply_A(mfs_plan p, MatvecFn A, const double *v, double *w, int prec, hipStr
 
 // One unrestarted GMRES attempt on A dx = r for every active system; x += dx.
 // target[s]: absolute residual target.  counts[s] += matvecs spent.  est[s]: final estimate.
+//
+// The least-squares update (Givens rotations, residual estimate, stopping test) and the
+// normalisation of the next Krylov vector run on the device, so the host enqueues
+// iteration j + 1 while iteration j runs: it only waits for the status block of iteration
+// j - 1 (one small asynchronous copy) to count matvecs, report progress and stop once no
+// system is live.  A system that stops drops out of the matvec mask on the device, before
+// the next matvec; the one iteration enqueued after the last system stopped finds no live
+// system and does no pair work.
 int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, const std::vector<double> &target,
                   int max_iter, std::vector<int> &active, std::vector<int> &counts, std::vector<double> &est,
                   hipStream_t s) {
@@ -1394,36 +1449,36 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         n_act += act[sy];
     }
     if (n_act == 0) return MFS_OK;
-    // host <-> device traffic of the loop goes through the plan's pinned buffers: the copies are
-    // asynchronous, and each buffer is rewritten only after the synchronisation that follows its copy
-    double *scale = p->h_scale;
-    for (int sy = 0; sy < S; ++sy) scale[sy] = act[sy] ? 1.0 / beta[sy] : 0.0;
-    MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale, S * sizeof(double), hipMemcpyHostToDevice, s));
-    MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), r, p->nrm.as<double>(), 1, V, s));
-    // Hessenberg columns and Givens data per system
-    std::vector<std::vector<double>> H(S, std::vector<double>((size_t)(max_iter + 1) * max_iter, 0.0));
-    std::vector<std::vector<double>> cs(S, std::vector<double>(max_iter)), sn(S, std::vector<double>(max_iter)),
-        g(S, std::vector<double>(max_iter + 1, 0.0));
-    std::vector<int> k(S, 0), live(act);
-    for (int sy = 0; sy < S; ++sy) g[sy][0] = beta[sy];
-    int32_t *act32 = p->h_act;
-    double *hbuf = p->h_dots, *nrm = p->h_dots + (size_t)S * 2 * ldh;
-    bool sent = false;  // the device mask equals live[] (it changes only when a system converges)
+    // initial state: targets, norms and the mask go up through pinned buffers (the last
+    // synchronisation, in sys_norms, ended every earlier copy out of them)
+    for (int sy = 0; sy < S; ++sy) {
+        p->h_init[sy] = target[sy];
+        p->h_init[S + sy] = std::isfinite(beta[sy]) ? beta[sy] : 0.0;
+        p->h_act[sy] = act[sy];
+    }
+    MFS_HIP_TRY(hipMemcpyAsync(p->gvInit.ptr, p->h_init, (size_t)S * 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, p->h_act, (size_t)S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    const GivensState st = p->givens();
+    MFS_TRY(launch_givens_init(st, s));
+    MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), r, st.scale, 1, V, s));
+    const size_t sb = p->stat_bytes();
+    auto slot = [&](int j) { return p->h_stat + (size_t)(j % mfs_plan_s::STAT_SLOTS) * sb; };
+    auto slot_est = [&](int j) { return reinterpret_cast<const double *>(slot(j)); };
+    auto slot_flag = [&](int j) { return reinterpret_cast<const int32_t *>(slot(j) + 8 * (size_t)S); };
+    auto slot_err = [&](int j) {
+        const int32_t *f = slot_flag(j);
+        return std::any_of(f, f + S, [](int32_t v) { return (v & 2) != 0; });
+    };
+    // Iteration j is enqueued before the status of iteration j - lag is read.  lag = 1 keeps
+    // the GPU busy across iterations; with a progress callback (meant for minutes-long
+    // solves) lag = 0, so every iteration is reported as it ends and a stop takes effect
+    // before the next one starts.
+    const int lag = p->progress ? 0 : 1;
+    for (int sy = 0; sy < S; ++sy) counts[sy] += act[sy];  // the matvec of iteration 0
+    int done = 0;                                          // iterations enqueued
+    bool empty_tail = false;  // the last enqueued iteration found no live system
     for (int j = 0; j < max_iter; ++j) {
-        int any = 0;
-        bool same = sent;
-        for (int sy = 0; sy < S; ++sy) {
-            same = same && act32[sy] == live[sy];
-            any |= live[sy];
-        }
-        if (!any) break;
-        if (!same) {
-            for (int sy = 0; sy < S; ++sy) act32[sy] = live[sy];
-            MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            sent = true;
-        }
         MFS_TRY(apply_A(p, A, V + (int64_t)j * n, w, prec, s));
-        for (int sy = 0; sy < S; ++sy) counts[sy] += live[sy];
         // classical Gram-Schmidt, twice
         double *dots = p->dots.as<double>();
         for (int pass = 0; pass < 2; ++pass) {
@@ -1435,76 +1490,60 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), w, 0, 1, w, p->dots_partial.as<double>(), ldp, s));
         MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
                                   p->nrm.as<double>(), 1, s));
-        MFS_HIP_TRY(hipMemcpyAsync(hbuf, dots, (size_t)S * 2 * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFS_HIP_TRY(hipMemcpyAsync(nrm, p->nrm.ptr, S * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFS_HIP_TRY(hipStreamSynchronize(s));
-        for (int sy = 0; sy < S; ++sy) {
-            scale[sy] = 0.0;
-            if (!live[sy]) continue;
-            double *h = &H[sy][(size_t)j * (max_iter + 1)];
-            for (int i = 0; i <= j; ++i) h[i] = hbuf[(size_t)sy * 2 * ldh + i] + hbuf[(size_t)sy * 2 * ldh + ldh + i];
-            const double hn = std::isnan(nrm[sy]) ? nrm[sy] : std::sqrt(std::max(0.0, nrm[sy]));
-            if (!std::isfinite(hn)) return fail(MFS_ENUMERIC, "non-finite Arnoldi vector");
-            h[j + 1] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[sy][i] * h[i] + sn[sy][i] * h[i + 1];
-                h[i + 1] = -sn[sy][i] * h[i] + cs[sy][i] * h[i + 1];
-                h[i] = t;
-            }
-            const double rho = std::hypot(h[j], h[j + 1]);
-            if (!(rho > 0.0)) {  // exact breakdown: the solution is in the current space
-                k[sy] = j;
-                live[sy] = 0;
-                continue;
-            }
-            cs[sy][j] = h[j] / rho;
-            sn[sy][j] = h[j + 1] / rho;
-            h[j] = rho;
-            h[j + 1] = 0.0;
-            g[sy][j + 1] = -sn[sy][j] * g[sy][j];
-            g[sy][j] = cs[sy][j] * g[sy][j];
-            k[sy] = j + 1;
-            est[sy] = std::fabs(g[sy][j + 1]);
-            if (est[sy] <= target[sy] || hn == 0.0) live[sy] = 0;
-            else scale[sy] = 1.0 / hn;
+        // the status slot written here was last read for iteration j - 3, before iteration
+        // j - 1 was enqueued
+        char *dslot = p->d_stat + (size_t)(j % mfs_plan_s::STAT_SLOTS) * sb;
+        MFS_TRY(launch_givens_step(st, j, reinterpret_cast<double *>(dslot),
+                                   reinterpret_cast<int32_t *>(dslot + 8 * (size_t)S), s));
+        MFS_HIP_TRY(hipEventRecord(p->stat_ev[j % mfs_plan_s::STAT_SLOTS], s));
+        MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, st.scale, 1, V + (int64_t)(j + 1) * n, s));
+        done = j + 1;
+        const int q = j - lag;  // the iteration whose status is read now
+        if (q < 0) continue;
+        MFS_HIP_TRY(hipEventSynchronize(p->stat_ev[q % mfs_plan_s::STAT_SLOTS]));
+        if (slot_err(q)) {
+            (void)hipStreamSynchronize(s);
+            return fail(MFS_ENUMERIC, "non-finite Arnoldi vector");
         }
-        if (p->progress) {
-            int n_live = 0, done = 0;
+        const int32_t *lv = slot_flag(q);  // bit 0: live (bit 1, an error, is handled above)
+        int n_live = 0;
+        for (int sy = 0; sy < S; ++sy) n_live += lv[sy] & 1;
+        if (p->progress) {  // counts hold the matvecs of iterations 0..q
+            const double *es = slot_est(q);
+            int most = 0;
             double worst = 0.0;
             for (int sy = 0; sy < S; ++sy) {
-                done = std::max(done, counts[sy]);
+                most = std::max(most, counts[sy]);
                 if (!act[sy]) continue;
-                n_live += live[sy];
                 const double bn = sy < (int)p->prog_bnorm.size() && p->prog_bnorm[sy] > 0 ? p->prog_bnorm[sy] : 1.0;
-                worst = std::max(worst, est[sy] / bn);
+                worst = std::max(worst, es[sy] / bn);
             }
-            if (p->progress(p->progress_user, done, n_live, worst) != 0) {
+            if (p->progress(p->progress_user, most, n_live, worst) != 0) {
                 p->stop_requested = true;
-                std::fill(live.begin(), live.end(), 0);
+                break;
             }
         }
-        if (j + 1 < max_iter) {
-            MFS_HIP_TRY(hipMemcpyAsync(p->nrm.ptr, scale, S * sizeof(double), hipMemcpyHostToDevice, s));
-            MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, p->nrm.as<double>(), 1, V + (int64_t)(j + 1) * n, s));
+        if (n_live == 0) {
+            empty_tail = lag == 1;
+            break;
         }
+        // iteration q + 1 runs its matvec on the systems live after iteration q: with lag 1 it
+        // is already enqueued, with lag 0 it is enqueued next unless the capacity ends here
+        if (lag == 1 || q + 1 < max_iter)
+            for (int sy = 0; sy < S; ++sy) counts[sy] += lv[sy] & 1;
     }
-    // back substitution per system, x += V y
-    const int kmax = *std::max_element(k.begin(), k.end());
-    std::vector<double> y((size_t)S * ldh, 0.0);
-    for (int sy = 0; sy < S; ++sy) {
-        if (!act[sy]) continue;
-        const int kk = k[sy];
-        for (int i = kk - 1; i >= 0; --i) {
-            double t = g[sy][i];
-            for (int c = i + 1; c < kk; ++c) t -= H[sy][(size_t)c * (max_iter + 1) + i] * y[(size_t)sy * ldh + c];
-            y[(size_t)sy * ldh + i] = t / H[sy][(size_t)i * (max_iter + 1) + i];
-        }
-    }
-    if (kmax > 0) {
-        MFS_HIP_TRY(hipMemcpyAsync(p->coef.ptr, y.data(), (size_t)S * ldh * sizeof(double), hipMemcpyHostToDevice, s));
-        MFS_TRY(launch_multi_axpy(nc, p->chunks.as<VecChunk>(), V, n, kmax, p->coef.as<double>(), ldh, 1.0, x, s));
-        MFS_HIP_TRY(hipStreamSynchronize(s));
-    }
+    // drain, then the final status and x += V y with y from the device back substitution
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    // the matvec of an empty tail iteration skipped every pair: keep its launch out of the
+    // pair-kernel timing (it is the last launch the timer recorded)
+    if (empty_tail && p->timing && A == matvec_impl && p->timer[prec].used > 0) --p->timer[prec].used;
+    if (slot_err(done - 1)) return fail(MFS_ENUMERIC, "non-finite Arnoldi vector");
+    const double *es = slot_est(done - 1);
+    for (int sy = 0; sy < S; ++sy)
+        if (act[sy]) est[sy] = es[sy];
+    MFS_TRY(launch_givens_solve(st, p->coef.as<double>(), ldh, done, s));
+    MFS_TRY(launch_multi_axpy(nc, p->chunks.as<VecChunk>(), V, n, done, p->coef.as<double>(), ldh, 1.0, x, s));
+    MFS_HIP_TRY(hipStreamSynchronize(s));
     return MFS_OK;
 }
 
@@ -1545,9 +1584,10 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
         for (int attempt = 0; attempt <= max_refine; ++attempt) {
             if (std::find(active.begin(), active.end(), 1) == active.end()) break;
             MFS_TRY(gmres_attempt(p, A, MFS_MIXED, r, x, target, max_iter, active, counts, est, s));
-            // true residual in FP64
-            std::vector<int32_t> act32(active.begin(), active.end());
-            MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, act32.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            // true residual in FP64 (the attempt ended with a synchronisation, so the pinned
+            // mask buffer is free)
+            std::copy(active.begin(), active.end(), p->h_act);
+            MFS_HIP_TRY(hipMemcpyAsync(p->sys_active.ptr, p->h_act, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
             MFS_TRY(A(p, x, p->Wv.as<double>(), MFS_FP64, p->sys_active.as<int32_t>(), s));
             for (int sy = 0; sy < S; ++sy) {
                 counts[sy] += active[sy];

@@ -247,4 +247,29 @@ int launch_add_inplace(int64_t n, const double *a, double *out, hipStream_t s);
 int launch_fill(int64_t n, double v, double *out, hipStream_t s);
 int launch_check_finite(int64_t n, const double *x, int32_t *flag, hipStream_t s);
 
+// Device state of the GMRES least-squares problems, one per system: the Hessenberg
+// columns are reduced by Givens rotations as they arrive, so |g_{j+1}| is the
+// residual estimate of iteration j (Saad & Schultz).  Arrays are per system, with
+// the leading dimensions given; R holds the rotated columns packed (column j at
+// j(j+1)/2, rows 0..j).
+struct GivensState {
+    int n_sys = 0, cap = 0, ldh = 0;   // systems, largest Krylov dimension, CGS row stride
+    const double *dots = nullptr;      // [n_sys][2][ldh] CGS coefficients of both passes
+    const double *nrm2 = nullptr;      // [n_sys] squared norm of the orthogonalised vector
+    const double *target = nullptr;    // [n_sys] absolute residual target
+    const double *beta = nullptr;      // [n_sys] initial residual norm
+    double *R = nullptr;               // [n_sys][cap (cap + 1) / 2]
+    double *cs = nullptr, *sn = nullptr;  // [n_sys][cap]
+    double *g = nullptr;               // [n_sys][cap + 1]
+    int32_t *k = nullptr;              // [n_sys] columns of the least-squares problem
+    int32_t *live = nullptr;           // [n_sys] systems still iterating (the matvec's mask)
+    double *scale = nullptr;           // [n_sys] 1 / h_{j+1,j} for live systems, else 0
+    double *est = nullptr;             // [n_sys] residual estimate
+};
+// Status block of one iteration, written by the step kernel into host-mapped memory:
+// est[n_sys] (residual estimates), then flag[n_sys] (bit 0: live, bit 1: non-finite column).
+int launch_givens_init(const GivensState &st, hipStream_t s);
+int launch_givens_step(const GivensState &st, int j, double *status_est, int32_t *status_flag, hipStream_t s);
+int launch_givens_solve(const GivensState &st, double *coef, int ld_coef, int nvec, hipStream_t s);
+
 }  // namespace mfs
