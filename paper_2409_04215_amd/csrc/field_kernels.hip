@@ -15,6 +15,7 @@
 // partial sums are added in wave order through LDS.  These fields are
 // evaluated after a solve (surface traction, pressure, residual checks), not
 // inside GMRES.
+#include "device_math.h"
 #include "mfs_internal.h"
 
 namespace mfs {
@@ -24,15 +25,6 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int WAVES = BLOCK / 64;
 constexpr int FLUSH = 64;
-
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    double e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    return y;
-}
 
 struct FieldArgs {
     const P2PItem *items;

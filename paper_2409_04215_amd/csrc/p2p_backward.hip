@@ -19,6 +19,7 @@
 // (wave-uniform loop, scalar loads, SGPR operands), the partial gradients added
 // in wave order through LDS, same-body handling and mixed FP32-pair /
 // FP64-accumulation precision exactly as there.
+#include "device_math.h"
 #include "mfs_internal.h"
 
 namespace mfs {
@@ -28,15 +29,6 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int WAVES = BLOCK / 64;
 constexpr int FLUSH = 64;
-
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    double e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    return y;
-}
 
 struct GradArgs {
     const P2PItem *items;

@@ -28,11 +28,12 @@
 //    v_rsq_f32; per run of at most FLUSH sources the FP32 partial is added
 //    to an FP64 accumulator.
 //  * FP64 variant: the same walk in FP64, 1/sqrt from v_rsq_f64 refined by
-//    two Newton steps y <- y + y (1 - r^2 y^2) / 2.
+//    one third-order step (rsqrt_f64 in device_math.h).
 //  * Same-body pairs: a source body equal to every active lane's own body is
 //    skipped wave-uniformly; a body shared by only some lanes is evaluated
 //    and its partial discarded per lane (select, not multiply), so no masking
 //    sits inside the pair loop.
+#include "device_math.h"
 #include "mfs_internal.h"
 
 namespace mfs {
@@ -86,15 +87,6 @@ __device__ __forceinline__ void wave_range(int b0, int b1, int wv, int &j0, int 
     const int q = (b1 - b0 + WAVES - 1) / WAVES;
     j0 = min(b0 + wv * q, b1);
     j1 = min(j0 + q, b1);
-}
-
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    double e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-r2 * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    return y;
 }
 
 struct KernelArgs {
