@@ -250,7 +250,11 @@ int mfs_matvec(mfs_plan plan, const double *gamma, double *out, int prec, void *
 int mfs_matvec_adjoint(mfs_plan plan, const double *w, double *out, int prec, void *stream);
 
 /* GMRES for A gamma = b (unrestarted per attempt, x0 = 0, classical
- * Gram-Schmidt with reorthogonalisation, Givens rotations on the host, FP64).
+ * Gram-Schmidt with reorthogonalisation, Givens rotations, FP64; the
+ * least-squares update and the stopping test run on the device, and the host
+ * enqueues each iteration before it reads the status of the one before, so
+ * the GPU does not wait for it (with a progress callback set it reads every
+ * status first; the results are the same).
  * Every system stops on its own when ||r||_2 <= tol ||b||_2 (the iteration
  * aims at tol/2, a margin for the outputs' error).  With a MIXED
  * plan the Krylov matvec is the mixed one; each attempt ends with an FP64

@@ -700,7 +700,7 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
         MFS_TRY(Vb.reserve((size_t)B * snn * sizeof(double)));
         MFS_TRY(Sv.reserve((size_t)B * n * sizeof(double)));
         MFS_TRY(E.reserve((size_t)B * n * sizeof(double)));
-        MFS_TRY(info.reserve((size_t)B * 2 * sizeof(rocblas_int)));
+        MFS_TRY(info.reserve((size_t)B * sizeof(rocblas_int)));
         // geometry of every factor of the batch, then assembly of each S_L
         int maxM = 0;
         std::vector<double> hp, hg;
@@ -731,12 +731,11 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
                                        p->formulation == MFS_RESISTANCE, SL.as<double>() + q * smn,
                                        work.as<double>(), s));
         }
-        MFS_TRY(E.reserve((size_t)B * 2 * sizeof(double)));
-        rocblas_status st = rocsolver_dgesvdj_strided_batched(
-            h, rocblas_svect_singular, rocblas_svect_singular, m, n, SL.as<double>(), m, smn, 0.0, E.as<double>(),
-            100, info.as<rocblas_int>() + B, Sv.as<double>(), n, Ub.as<double>(), m, smn, Vb.as<double>(), n, snn,
+        rocblas_status st = rocsolver_dgesvd_strided_batched(
+            h, rocblas_svect_singular, rocblas_svect_singular, m, n, SL.as<double>(), m, smn, Sv.as<double>(), n,
+            Ub.as<double>(), m, smn, Vb.as<double>(), n, snn, E.as<double>(), n, rocblas_outofplace,
             info.as<rocblas_int>(), B);
-        if (st != rocblas_status_success) return fail(MFS_EHIP, "rocsolver_dgesvdj_strided_batched failed");
+        if (st != rocblas_status_success) return fail(MFS_EHIP, "rocsolver_dgesvd_strided_batched failed");
         std::vector<double> sv((size_t)B * n);
         std::vector<rocblas_int> hinfo(B);
         MFS_HIP_TRY(hipMemcpyAsync(sv.data(), Sv.ptr, sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));

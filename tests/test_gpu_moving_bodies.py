@@ -137,3 +137,25 @@ def test_gradient_step_by_moving_bodies():
     J_back, g_back = loss_and_grad()
     assert J_back == J0 and np.array_equal(g_back, g0)
     plan.close()
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_moved_resistance_plan_equals_new_plan(kind):
+    """The Dirichlet data of a resistance solve (rigid motion at the moved
+    collocation points) follows the bodies too."""
+    mfs = _mfs()
+    a, b = _pair(kind, 4, 148)
+    data = np.random.default_rng(149).standard_normal(4 * (6 if kind == W.STOKES else 1))
+    ref = O.ResistanceProblem.from_workload(b).solve(data.reshape(4, -1) if kind == W.STOKES else data,
+                                                     tol=1e-12)["out"]
+    moved = mfs.Plan.from_workload(a, mfs.FP64, formulation=mfs.RESISTANCE)
+    moved.solve(_dev(data), tol=1e-10)
+    moved.set_bodies(b.centre, b.rot)
+    fresh = mfs.Plan.from_workload(b, mfs.FP64, formulation=mfs.RESISTANCE)
+    out_m, info_m = moved.solve(_dev(data), tol=1e-10)
+    out_f, _ = fresh.solve(_dev(data), tol=1e-10)
+    assert info_m["status"] == mfs.MFS_OK
+    assert torch.equal(out_m, out_f)
+    assert rel_inf(out_m.cpu().numpy(), np.asarray(ref).reshape(-1)) <= 1e-8
+    moved.close()
+    fresh.close()

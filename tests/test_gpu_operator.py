@@ -171,3 +171,37 @@ def test_progress_callback_and_early_stop():
     plan.set_progress(None)
     _, iters, _, st = plan.gmres_solve(b, tol=1e-8)
     assert st == mfs.MFS_OK and iters[0] > 3
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "MIXED"])
+def test_lookahead_gmres_equals_reported_gmres(prec_name):
+    """Without a progress callback the host enqueues each GMRES iteration before
+    reading the previous one's status; with one it reads every status first.
+    The device arithmetic is the same, so gamma, the matvec counts and the
+    residuals agree bit for bit: in a batch where systems stop at different
+    iterations, and when max_iter ends the solve first (MFS_NOT_CONVERGED)."""
+    mfs = _mfs()
+    prec = getattr(mfs, prec_name)
+    a = W.small_cluster(4, W.STOKES, 45, 130, seed=151)
+    b = W.small_cluster(3, W.LAPLACE, 45, 130, seed=152)
+    b.centre = b.centre + 60.0
+    sh = a.shapes[0]
+    plan = mfs.Plan(prec, [0, 4, 7], [W.STOKES, W.LAPLACE], np.concatenate([a.centre, b.centre]),
+                    np.concatenate([a.rot, b.rot]), np.zeros(7, np.int32), [sh.src], [sh.trg])
+    net = _dev(np.concatenate([a.net[0].reshape(-1), b.net[0].reshape(-1)]))
+    rhs, _ = plan.rhs(net)
+    for tol, max_iter in ((1e-9, 200), (1e-12, 3)):
+        plan.set_progress(None)
+        g1, it1, rr1, st1 = plan.gmres_solve(rhs, tol=tol, max_iter=max_iter)
+        calls = []
+        plan.set_progress(lambda mv, act, rr: calls.append(mv) and False)
+        g2, it2, rr2, st2 = plan.gmres_solve(rhs, tol=tol, max_iter=max_iter)
+        plan.set_progress(None)
+        print(prec_name, tol, max_iter, "iters", it1, it2, "status", st1, st2)
+        assert st1 == st2 and torch.equal(g1, g2)
+        assert list(it1) == list(it2) and np.array_equal(rr1, rr2)
+        if max_iter == 3:
+            assert st1 == mfs.MFS_NOT_CONVERGED
+            if prec == mfs.FP64:  # one attempt of three iterations (mixed plans refine on top)
+                assert list(it1) == [3, 3] and max(calls) == 3
+    plan.close()
