@@ -293,6 +293,8 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="fix the pair-sum launch shape instead of autotuning: TPL,WORK_ITEMS,PERSISTENT "
                          "(e.g. 1,16384,0; used for counter runs, which must repeat one shape)")
+    ap.add_argument("--factorization", default="svd", choices=("svd", "qr"),
+                    help="one-body factorisation of the plans: rocSOLVER SVD or the library's Householder QR")
     args = ap.parse_args()
     large = args.workload in LARGE
     args.steps = args.steps if args.steps is not None else (1 if large else 5)
@@ -321,12 +323,13 @@ def main():
     net = torch.tensor(np.concatenate([n.reshape(-1) for n in wl.net]), dtype=torch.float64, device="cuda")
 
     t0 = time.perf_counter()
-    plan_mx = mfs.Plan.from_workload(wl, mfs.MIXED)
+    fact = mfs.FACTOR_QR if args.factorization == "qr" else mfs.FACTOR_SVD
+    plan_mx = mfs.Plan.from_workload(wl, mfs.MIXED, factorization=fact)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     if args.counter_sweep:
         return counter_sweep(plan_mx, mfs, torch, np)
-    plan_64 = mfs.Plan.from_workload(wl, mfs.FP64) if args.fp64_steps > 0 else None
+    plan_64 = mfs.Plan.from_workload(wl, mfs.FP64, factorization=fact) if args.fp64_steps > 0 else None
     max_iter = 100 if large else 200
     if large:
         t_start = time.perf_counter()
@@ -474,7 +477,8 @@ def main():
                    "proxies_per_body": int(wl.shapes[0].src.shape[0]),
                    "collocation_per_body": int(wl.shapes[0].trg.shape[0]),
                    "kernel": " + ".join(kind_name[k] for k in kinds) + (" + centre gradient" if grad else ""),
-                   "gmres_tol": args.tol, "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total},
+                   "gmres_tol": args.tol, "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total,
+                   "factorization": args.factorization},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": round(traffic["traffic_bytes"]) if traffic else None,

@@ -181,6 +181,17 @@ typedef struct mfs_plan_s *mfs_plan;
  *   Algorithm 1). */
 enum { MFS_MOBILITY = 0, MFS_RESISTANCE = 1 };
 
+/* Factorisation of the one-body blocks (Section 2.3, eq. (pseudo)).
+ * MFS_FACTOR_SVD: S_L = U Sigma V^T by rocSOLVER's batched FP64 SVD
+ *   (bidiagonal QR); the plan applies S_L^+ = (V Sigma^-1)(U^T .).
+ * MFS_FACTOR_QR: S_L = Q R by the library's batched FP64 Householder QR;
+ *   for full column rank S_L^+ = R^-1 Q^T, the same operator, applied in the
+ *   same two steps ((R^-1)(Q^T .)), with R^-1 from triangular solves.  Much
+ *   faster to build; mfs_plan_sizes then reports 1 / (||R||_F ||R^-1||_F),
+ *   a lower bound of sigma_min / sigma_max, and the rank check uses that
+ *   bound.  At most 8192 columns (3N Stokes, N Laplace) per block. */
+enum { MFS_FACTOR_SVD = 0, MFS_FACTOR_QR = 1 };
+
 typedef struct {
     int32_t precision;             /* MFS_MIXED or MFS_FP64: matvec used inside GMRES */
     double mu;                     /* Stokes viscosity (> 0) */
@@ -196,6 +207,7 @@ typedef struct {
     const double *shape_src;       /* [host] concatenated local proxies, sum(N) x 3 */
     const double *shape_trg;       /* [host] concatenated local collocation points, sum(M) x 3 */
     int32_t formulation;           /* MFS_MOBILITY (0, also for a zero-initialised descriptor) or MFS_RESISTANCE */
+    int32_t factorization;         /* MFS_FACTOR_SVD (0, the default) or MFS_FACTOR_QR */
 } mfs_plan_desc;
 
 /* Builds a plan: uploads geometry, assembles S_L (MFS_MOBILITY) or S^(kk)

@@ -360,6 +360,7 @@ struct Factor {
 struct mfs_plan_s {
     int prec = MFS_MIXED;
     int formulation = MFS_MOBILITY;
+    int factorization = MFS_FACTOR_SVD;
     double mu = 1.0;
     int64_t n_sys = 0, n_body = 0;
     std::vector<int64_t> sys_body_ptr;
@@ -690,7 +691,7 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
             batches.back().push_back(keyed[i].second);
         }
     }
-    DevBuf SL, Ub, Vb, Sv, E, info, work, pts, gi, inv;
+    DevBuf SL, Ub, Vb, Sv, E, info, work, pts, gi, inv, tau;
     for (auto &bt : batches) {
         const int B = (int)bt.size();
         const int m = p->factors[bt[0]].dM, n = p->factors[bt[0]].dN;
@@ -730,6 +731,32 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
             MFS_TRY(launch_assemble_SL(F.kind, M, N, P, P + 3 * (size_t)M, gi.as<double>() + 36 * q, p->mu,
                                        p->formulation == MFS_RESISTANCE, SL.as<double>() + q * smn,
                                        work.as<double>(), s));
+        }
+        if (p->factorization == MFS_FACTOR_QR) {
+            // S_L = Q R (library QR): U^T <- Q^T, U <- Q, W <- R^-1, W^T <- R^-T
+            MFS_TRY(tau.reserve((size_t)B * n * sizeof(double)));
+            MFS_TRY(qr_inverse_batched(B, SL.as<double>(), m, n, smn, Ub.as<double>(), smn, Vb.as<double>(), snn,
+                                       tau.as<double>(), Sv.as<double>(), s));
+            std::vector<double> rat(B);
+            MFS_HIP_TRY(hipMemcpyAsync(rat.data(), Sv.ptr, B * sizeof(double), hipMemcpyDeviceToHost, s));
+            MFS_HIP_TRY(hipStreamSynchronize(s));
+            double *A64 = p->A64.as<double>();
+            float *A32 = p->A32.as<float>();
+            for (int q = 0; q < B; ++q) {
+                Factor &F = p->factors[bt[q]];
+                F.ratio = std::isfinite(rat[q]) ? rat[q] : 0.0;
+                p->min_ratio = std::min(p->min_ratio, F.ratio);
+                if (!(F.ratio > 1e-14))
+                    return fail(MFS_ENUMERIC, "QR: 1/(|R|_F |R^-1|_F) = " + std::to_string(F.ratio) + " <= 1e-14");
+                const double *Q = Ub.as<double>() + q * smn, *X = Vb.as<double>() + q * snn;
+                MFS_TRY(launch_make_factor(n, m, Q, m, false, nullptr, nullptr, A64 + F.ut_off, A32 + F.ut_off, s));
+                MFS_TRY(launch_make_factor(m, n, Q, m, true, nullptr, nullptr, A64 + F.u_off, A32 + F.u_off, s));
+                // X column-major (ld n): W[r][c] = X[c n + r], W^T[r][c] = X[r n + c]
+                MFS_TRY(launch_make_factor(n, n, X, n, true, nullptr, nullptr, A64 + F.w_off, A32 + F.w_off, s));
+                MFS_TRY(launch_make_factor(n, n, X, n, false, nullptr, nullptr, A64 + F.wt_off, A32 + F.wt_off, s));
+            }
+            MFS_HIP_TRY(hipStreamSynchronize(s));
+            continue;
         }
         rocblas_status st = rocsolver_dgesvd_strided_batched(
             h, rocblas_svect_singular, rocblas_svect_singular, m, n, SL.as<double>(), m, smn, Sv.as<double>(), n,
@@ -919,6 +946,8 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     if (d->precision != MFS_MIXED && d->precision != MFS_FP64) return fail(MFS_EINVAL, "unknown precision");
     if (d->formulation != MFS_MOBILITY && d->formulation != MFS_RESISTANCE)
         return fail(MFS_EINVAL, "unknown formulation");
+    if (d->factorization != MFS_FACTOR_SVD && d->factorization != MFS_FACTOR_QR)
+        return fail(MFS_EINVAL, "unknown factorization");
     if (d->n_sys < 1 || !d->sys_body_ptr || !d->sys_kind) return fail(MFS_EINVAL, "bad system description");
     if (d->sys_body_ptr[0] != 0) return fail(MFS_EINVAL, "sys_body_ptr[0] must be 0");
     for (int64_t sy = 0; sy < d->n_sys; ++sy) {
@@ -950,6 +979,7 @@ int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *d, void *stream) {
     std::unique_ptr<mfs_plan_s> p(new mfs_plan_s());
     p->prec = d->precision;
     p->formulation = d->formulation;
+    p->factorization = d->factorization;
     p->n_shape = d->n_shape;
     p->shape_of_body.assign(d->shape_of_body, d->shape_of_body + nb);
     p->mu = d->mu;

@@ -269,6 +269,13 @@ struct GivensState {
 // Status block of one iteration, written by the step kernel into host-mapped memory:
 // est[n_sys] (residual estimates), then flag[n_sys] (bit 0: live, bit 1: non-finite column).
 int launch_givens_init(const GivensState &st, hipStream_t s);
+
+// Batched FP64 Householder QR of column-major m x n matrices A (leading dimension m, m >= n,
+// n <= 8192), factor_kernels.hip: A is overwritten by R (upper triangle) and the reflectors,
+// Q (m x n, leading dimension m) and X = R^-1 (n x n, leading dimension n) are written, and
+// ratio[b] = 1 / (||R||_F ||R^-1||_F).  tau: [batch][n] scratch.
+int qr_inverse_batched(int batch, double *A, int m, int n, int64_t stride_a, double *Q, int64_t stride_q, double *X,
+                       int64_t stride_x, double *tau, double *ratio, hipStream_t s);
 int launch_givens_step(const GivensState &st, int j, double *status_est, int32_t *status_flag, hipStream_t s);
 int launch_givens_solve(const GivensState &st, double *coef, int ld_coef, int nvec, hipStream_t s);
 

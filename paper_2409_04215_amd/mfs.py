@@ -22,6 +22,7 @@ LAPLACE, STOKES = 0, 1
 FP64, MIXED = 0, 1
 SKIP_SAME_BODY, ACCUMULATE, PROJECT, TRANSPOSE = 1, 2, 4, 8
 MOBILITY, RESISTANCE = 0, 1
+FACTOR_SVD, FACTOR_QR = 0, 1
 
 _lib = None
 
@@ -46,6 +47,7 @@ class PlanDesc(ctypes.Structure):
         ("sys_body_ptr", _i64p), ("sys_kind", _i32p), ("centre", _dp), ("rot", _dp),
         ("shape_of_body", _i32p), ("n_shape", ctypes.c_int64), ("shape_n_src", _i32p),
         ("shape_n_trg", _i32p), ("shape_src", _dp), ("shape_trg", _dp), ("formulation", ctypes.c_int32),
+        ("factorization", ctypes.c_int32),
     ]
 
 
@@ -228,11 +230,13 @@ class Plan:
     """A resident solve plan (see mfs_plan_create in mfs.h)."""
 
     def __init__(self, precision: int, sys_body_ptr, sys_kind, centre, rot, shape_of_body, shape_src: Sequence,
-                 shape_trg: Sequence, mu: float = 1.0, device="cuda", stream=None, formulation: int = MOBILITY):
+                 shape_trg: Sequence, mu: float = 1.0, device="cuda", stream=None, formulation: int = MOBILITY,
+                 factorization: int = FACTOR_SVD):
         self.device = torch.device(device)
         self._h = ctypes.c_void_p()
         self.precision = int(precision)
         self.formulation = int(formulation)
+        self.factorization = int(factorization)
         self.sys_body_ptr = _host_i64(sys_body_ptr)
         self.sys_kind = np.ascontiguousarray(np.asarray(sys_kind, dtype=np.int32))
         self.centre = np.ascontiguousarray(np.asarray(centre, dtype=np.float64))
@@ -258,6 +262,7 @@ class Plan:
         d.shape_src = self.shape_src.ctypes.data_as(_dp)
         d.shape_trg = self.shape_trg.ctypes.data_as(_dp)
         d.formulation = self.formulation
+        d.factorization = self.factorization
         with torch.cuda.device(self.device):
             _check(lib().mfs_plan_create(ctypes.byref(self._h), ctypes.byref(d), _stream(stream)), "mfs_plan_create")
         ng, nl, nn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -269,10 +274,10 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, precision: int = MIXED, device="cuda", stream=None,
-                      formulation: int = MOBILITY) -> "Plan":
+                      formulation: int = MOBILITY, factorization: int = FACTOR_SVD) -> "Plan":
         return cls(precision, wl.sys_body_ptr, wl.sys_kind, wl.centre, wl.rot, wl.shape_of_body,
                    [s.src for s in wl.shapes], [s.trg for s in wl.shapes], mu=wl.mu, device=device, stream=stream,
-                   formulation=formulation)
+                   formulation=formulation, factorization=factorization)
 
     def set_bodies(self, centre, rot, stream=None):
         """Moves the bodies (new centres [n_body, 3] and rotations [n_body, 3, 3]);

@@ -1,0 +1,95 @@
+"""The library's batched FP64 Householder QR as the one-body factorisation
+(MFS_FACTOR_QR): S_L = Q R, S_L^+ = R^-1 Q^T, applied as (R^-1)(Q^T .).
+
+For full column rank this is the pseudo-inverse the SVD gives (Section 2.3),
+so a QR plan must meet the same bars against the oracle (which uses the SVD)
+as an SVD plan, and agree with an SVD plan to FP64 rounding amplified by the
+conditioning of S_L:
+* S_L^+ apply and Ag: FP64 1e-10, mixed 5e-3 / 1e-4 (as for SVD plans);
+* solves: FP64 at tol 1e-10 within 1e-8 of the oracle, mixed at tol 1e-7
+  within 1e-6; ellipsoids_100 against the stored oracle solutions as in the
+  full-size tests (mixed at tol 1e-6: 1e-5);
+* the reported ratio 1/(|R|_F |R^-1|_F) lies between sigma_min/sigma_max / n
+  and sigma_min/sigma_max (n = columns);
+* a rank-deficient block (two proxies at one point) is refused.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import net_flat, rel_inf
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_qr_plan_matches_oracle_and_svd_plan(kind):
+    mfs = _mfs()
+    wl = W.small_cluster(5, kind, 45, 301, seed=161)
+    pr = O.Problem.from_workload(wl)
+    g = W.random_vector(pr.n_gamma, 162)
+    ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
+    ref_A = pr.matvec(g)
+    sol = pr.solve(wl.net[0], tol=1e-12)
+    svd = mfs.Plan.from_workload(wl, mfs.FP64)
+    for prec, tol_p, tol_A, solve_tol, bar in ((mfs.FP64, 1e-10, 1e-10, 1e-10, 1e-8),
+                                                (mfs.MIXED, 5e-3, 1e-4, 1e-7, 1e-6)):
+        qr = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
+        e = (rel_inf(qr.precond_apply(_dev(g), 0, prec).cpu().numpy(), ref_p),
+             rel_inf(qr.matvec(_dev(g), prec).cpu().numpy(), ref_A))
+        out, info = qr.solve(_dev(net_flat(wl)), tol=solve_tol)
+        es = rel_inf(out.cpu().numpy(), sol["out"])
+        print(kind, prec, "S_L^+ apply, A g", e, "solve", es, "iters", info["iters"], "ratio bound", qr.min_sigma_ratio,
+              "svd ratio", svd.min_sigma_ratio)
+        assert e[0] <= tol_p and e[1] <= tol_A
+        assert info["status"] == mfs.MFS_OK and es <= bar
+        if prec == mfs.FP64:
+            d = rel_inf(qr.matvec(_dev(g), mfs.FP64).cpu().numpy(), svd.matvec(_dev(g), mfs.FP64).cpu().numpy())
+            assert d <= 1e-10
+            ncol = (3 if kind == W.STOKES else 1) * wl.shapes[0].src.shape[0]
+            assert svd.min_sigma_ratio / ncol <= qr.min_sigma_ratio <= svd.min_sigma_ratio * (1 + 1e-9)
+        qr.close()
+    svd.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kind,fname", [(W.STOKES, "ellipsoids_100_stokes_U.txt"),
+                                        (W.LAPLACE, "ellipsoids_100_laplace_phi.txt")])
+def test_qr_plan_ellipsoids_100_vs_stored_oracle(kind, fname):
+    mfs = _mfs()
+    wl = W.ellipsoids_100(kind)
+    ref = np.loadtxt(os.path.join(GOLDEN, fname)).reshape(-1)
+    net = _dev(net_flat(wl))
+    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-6, 1e-5)):
+        plan = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
+        out, info = plan.solve(net, tol=tol)
+        e = rel_inf(out.cpu().numpy(), ref)
+        print(f"QR kind={kind} prec={prec} tol={tol:g} iters={info['iters']} err={e:.2e}")
+        assert info["status"] == mfs.MFS_OK and e <= bar
+        plan.close()
+
+
+@pytest.mark.parametrize("fact", ["FACTOR_SVD", "FACTOR_QR"])
+def test_rank_deficient_block_is_refused(fact):
+    mfs = _mfs()
+    wl = W.small_cluster(2, W.LAPLACE, 40, 100, seed=163)
+    src = wl.shapes[0].src.copy()
+    src[7] = src[3]  # two proxies at one point: two equal columns of S_L
+    wl.shapes[0].src = src
+    with pytest.raises(mfs.MfsError) as err:
+        mfs.Plan.from_workload(wl, mfs.FP64, factorization=getattr(mfs, fact))
+    assert err.value.status == mfs.MFS_ENUMERIC
