@@ -93,3 +93,38 @@ def test_rank_deficient_block_is_refused(fact):
     with pytest.raises(mfs.MfsError) as err:
         mfs.Plan.from_workload(wl, mfs.FP64, factorization=getattr(mfs, fact))
     assert err.value.status == mfs.MFS_ENUMERIC
+
+
+@pytest.mark.timeout(600)
+def test_type_t_cluster_both_factorizations():
+    """20 Type T ellipsoids built like the 10^4 case (N = 658, M = 842: blocks of
+    2526 x 1974): solves of SVD and QR plans against the oracle."""
+    mfs = _mfs()
+    wl = W.type_t_cluster(20, W.STOKES, 164)
+    ref = O.Problem.from_workload(wl).solve(wl.net[0], tol=1e-12)["out"]
+    net = _dev(net_flat(wl))
+    for fact in (mfs.FACTOR_SVD, mfs.FACTOR_QR):
+        for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-6, 1e-5)):
+            plan = mfs.Plan.from_workload(wl, prec, factorization=fact)
+            out, info = plan.solve(net, tol=tol)
+            e = rel_inf(out.cpu().numpy(), ref)
+            print("type T", "QR" if fact else "SVD", prec, "iters", info["iters"], "err", e, "ratio", plan.min_sigma_ratio)
+            assert info["status"] == mfs.MFS_OK and e <= bar
+            plan.close()
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_qr_resistance_plan(kind):
+    """The Dirichlet formulation factors the bare S^(kk) blocks (eq. (2sysprec)); QR there too."""
+    mfs = _mfs()
+    wl = W.small_cluster(4, kind, 45, 301, seed=165)
+    rng = np.random.default_rng(166)
+    data = rng.standard_normal((4, 6)) if kind == W.STOKES else rng.standard_normal(4)
+    sol = O.ResistanceProblem.from_workload(wl).solve(data, tol=1e-12)
+    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-7, 1e-6)):
+        plan = mfs.Plan.from_workload(wl, prec, formulation=mfs.RESISTANCE, factorization=mfs.FACTOR_QR)
+        out, info = plan.solve(_dev(data), tol=tol)
+        e = rel_inf(out.cpu().numpy(), np.asarray(sol["out"]).reshape(-1))
+        print("resistance QR", kind, prec, "err", e)
+        assert info["status"] == mfs.MFS_OK and e <= bar
+        plan.close()
