@@ -149,19 +149,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, const GemmTile *
     }
 }
 
-// C[:, col] = sum over split slices (fixed order); one block per column
+// C[:, col] = sum over split slices (fixed order); blocks over (column, 256 rows), one thread per row
 template <class T>
 __global__ void gemm_reduce_kernel(const int32_t *__restrict__ col_group, const GemmGroup *__restrict__ groups,
                                    const T *__restrict__ partial, int64_t part_col_stride, int64_t part_split_stride,
                                    int n_split, T *__restrict__ C, const int64_t *__restrict__ c_col_off) {
     const int col = blockIdx.x;
     const int M = groups[col_group[col]].M;
-    T *out = C + c_col_off[col];
-    for (int m = threadIdx.x; m < M; m += blockDim.x) {
-        T s = 0;
-        for (int sp = 0; sp < n_split; ++sp) s += partial[sp * part_split_stride + (int64_t)col * part_col_stride + m];
-        out[m] = s;
-    }
+    const int m = blockIdx.y * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    T s = 0;
+    for (int sp = 0; sp < n_split; ++sp) s += partial[sp * part_split_stride + (int64_t)col * part_col_stride + m];
+    C[c_col_off[col] + m] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -624,8 +623,8 @@ int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, con
                                                           c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
     if (part) {
-        gemm_reduce_kernel<float><<<G.n_cols, 256, 0, s>>>(G.col_group, G.groups, part, G.part_col_stride,
-                                                           G.part_split_stride, G.n_split, C, c_col_off);
+        gemm_reduce_kernel<float><<<dim3(G.n_cols, (unsigned)((G.part_col_stride + 255) / 256)), 256, 0, s>>>(
+            G.col_group, G.groups, part, G.part_col_stride, G.part_split_stride, G.n_split, C, c_col_off);
         MFS_HIP_TRY(hipGetLastError());
     }
     return MFS_OK;
@@ -639,8 +638,8 @@ int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, c
                                                             c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
     if (part) {
-        gemm_reduce_kernel<double><<<G.n_cols, 256, 0, s>>>(G.col_group, G.groups, part, G.part_col_stride,
-                                                            G.part_split_stride, G.n_split, C, c_col_off);
+        gemm_reduce_kernel<double><<<dim3(G.n_cols, (unsigned)((G.part_col_stride + 255) / 256)), 256, 0, s>>>(
+            G.col_group, G.groups, part, G.part_col_stride, G.part_split_stride, G.n_split, C, c_col_off);
         MFS_HIP_TRY(hipGetLastError());
     }
     return MFS_OK;
