@@ -12,12 +12,10 @@ namespace {
 
 constexpr int DOT_GROUP = 8;
 
-// partial[c][i] = sum_{n in chunk c} V[i][n] w[n], i < nvec
-__global__ __launch_bounds__(256) void multi_dot_kernel(const VecChunk *__restrict__ chunks, const double *__restrict__ V,
-                                                        int64_t ldv, int nvec, const double *__restrict__ w,
-                                                        double *__restrict__ partial, int ld_partial) {
-    __shared__ double sh[4][DOT_GROUP];
-    const VecChunk ch = chunks[blockIdx.x];
+// out[i] = sum_{n in chunk} V[i][n] w[n], i < nvec (one workgroup of 256 threads per chunk;
+// thread t visits n = begin + t, begin + t + 256, ...)
+__device__ __forceinline__ void chunk_dots(const VecChunk ch, const double *V, int64_t ldv, int nvec,
+                                           const double *w, double *__restrict__ out, double (*sh)[DOT_GROUP]) {
     const int tid = threadIdx.x;
     for (int i0 = 0; i0 < nvec; i0 += DOT_GROUP) {
         double acc[DOT_GROUP];
@@ -40,9 +38,35 @@ __global__ __launch_bounds__(256) void multi_dot_kernel(const VecChunk *__restri
 #pragma unroll
             for (int q = 0; q < DOT_GROUP; ++q) sh[tid >> 6][q] = acc[q];
         __syncthreads();
-        if (tid < ni) partial[(int64_t)blockIdx.x * ld_partial + i0 + tid] = sh[0][tid] + sh[1][tid] + sh[2][tid] + sh[3][tid];
+        if (tid < ni) out[i0 + tid] = sh[0][tid] + sh[1][tid] + sh[2][tid] + sh[3][tid];
         __syncthreads();
     }
+}
+
+// partial[c][i] = sum_{n in chunk c} V[i][n] w[n], i < nvec
+__global__ __launch_bounds__(256) void multi_dot_kernel(const VecChunk *__restrict__ chunks, const double *__restrict__ V,
+                                                        int64_t ldv, int nvec, const double *__restrict__ w,
+                                                        double *__restrict__ partial, int ld_partial) {
+    __shared__ double sh[4][DOT_GROUP];
+    chunk_dots(chunks[blockIdx.x], V, ldv, nvec, w, partial + (int64_t)blockIdx.x * ld_partial, sh);
+}
+
+// w[n] += sign * sum_i V[i][n] coef[sys(n)][i] (i < nvec), then on the updated chunk
+// partial[c][i] = sum_n D[i][n] w[n] (i < ndot): an axpy and the next dot products in one pass.
+// Each thread reads back only the w entries it wrote, so no barrier separates the two.
+__global__ __launch_bounds__(256) void axpy_dot_kernel(const VecChunk *__restrict__ chunks, const double *__restrict__ V,
+                                                       int64_t ldv, int nvec, const double *__restrict__ coef, int ld_coef,
+                                                       double sign, double *w, const double *D, int64_t ldd, int ndot,
+                                                       double *__restrict__ partial, int ld_partial) {
+    __shared__ double sh[4][DOT_GROUP];
+    const VecChunk ch = chunks[blockIdx.x];
+    const double *cf = coef + (int64_t)ch.sys * ld_coef;
+    for (int64_t n = ch.begin + threadIdx.x; n < ch.end; n += 256) {
+        double acc = 0.0;
+        for (int i = 0; i < nvec; ++i) acc += V[(int64_t)i * ldv + n] * cf[i];
+        w[n] += sign * acc;
+    }
+    chunk_dots(ch, D, ldd, ndot, w, partial + (int64_t)blockIdx.x * ld_partial, sh);
 }
 
 // out[s][i] = sum over chunks of system s of partial[c][i]; one block per (i, s),
@@ -208,6 +232,16 @@ int launch_reduce_sys(int n_sys, const int32_t *sys_chunk_ptr, const double *par
                       double *out, int ld_out, hipStream_t s) {
     if (n_sys == 0 || nval == 0) return MFS_OK;
     reduce_sys_kernel<<<dim3(nval, n_sys), 256, 0, s>>>(sys_chunk_ptr, partial, ld_partial, out, ld_out);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_axpy_dot(int n_chunk, const VecChunk *chunks, const double *V, int64_t ldv, int nvec, const double *coef,
+                    int ld_coef, double sign, double *w, const double *D, int64_t ldd, int ndot, double *partial,
+                    int ld_partial, hipStream_t s) {
+    if (n_chunk == 0) return MFS_OK;
+    axpy_dot_kernel<<<n_chunk, 256, 0, s>>>(chunks, V, ldv, nvec, coef, ld_coef, sign, w, D, ldd, ndot, partial,
+                                            ld_partial);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -1509,17 +1509,18 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
     bool empty_tail = false;  // the last enqueued iteration found no live system
     for (int j = 0; j < max_iter; ++j) {
         MFS_TRY(apply_A(p, A, V + (int64_t)j * n, w, prec, s));
-        // classical Gram-Schmidt, twice
+        // classical Gram-Schmidt, twice: dots, then (axpy + the next dots) twice, the last
+        // dots being |w|^2
         double *dots = p->dots.as<double>();
-        for (int pass = 0; pass < 2; ++pass) {
-            MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), V, n, j + 1, w, p->dots_partial.as<double>(), ldp, s));
-            MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, j + 1,
-                                      dots + pass * ldh, 2 * ldh, s));
-            MFS_TRY(launch_multi_axpy(nc, p->chunks.as<VecChunk>(), V, n, j + 1, dots + pass * ldh, 2 * ldh, -1.0, w, s));
-        }
-        MFS_TRY(launch_multi_dot(nc, p->chunks.as<VecChunk>(), w, 0, 1, w, p->dots_partial.as<double>(), ldp, s));
-        MFS_TRY(launch_reduce_sys(S, p->sys_chunk_ptr.as<int32_t>(), p->dots_partial.as<double>(), ldp, 1,
-                                  p->nrm.as<double>(), 1, s));
+        const VecChunk *ck = p->chunks.as<VecChunk>();
+        double *part = p->dots_partial.as<double>();
+        const int32_t *scp = p->sys_chunk_ptr.as<int32_t>();
+        MFS_TRY(launch_multi_dot(nc, ck, V, n, j + 1, w, part, ldp, s));
+        MFS_TRY(launch_reduce_sys(S, scp, part, ldp, j + 1, dots, 2 * ldh, s));
+        MFS_TRY(launch_axpy_dot(nc, ck, V, n, j + 1, dots, 2 * ldh, -1.0, w, V, n, j + 1, part, ldp, s));
+        MFS_TRY(launch_reduce_sys(S, scp, part, ldp, j + 1, dots + ldh, 2 * ldh, s));
+        MFS_TRY(launch_axpy_dot(nc, ck, V, n, j + 1, dots + ldh, 2 * ldh, -1.0, w, w, 0, 1, part, ldp, s));
+        MFS_TRY(launch_reduce_sys(S, scp, part, ldp, 1, p->nrm.as<double>(), 1, s));
         // the status slot written here was last read for iteration j - 3, before iteration
         // j - 1 was enqueued
         char *dslot = p->d_stat + (size_t)(j % mfs_plan_s::STAT_SLOTS) * sb;

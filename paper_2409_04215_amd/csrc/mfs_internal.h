@@ -242,6 +242,11 @@ int launch_multi_axpy(int n_chunk, const VecChunk *chunks, const double *V, int6
                       const double *coef, int ld_coef, double sign, double *w, hipStream_t s);
 int launch_scale_sys(int n_chunk, const VecChunk *chunks, const double *w, const double *scale, int ld_scale,
                      double *out, hipStream_t s);
+// w += sign * V coef (as launch_multi_axpy), then partial[c][i] = D[i] . w over chunk c for i < ndot
+// (as launch_multi_dot on the updated w), in one kernel with the same arithmetic order.
+int launch_axpy_dot(int n_chunk, const VecChunk *chunks, const double *V, int64_t ldv, int nvec, const double *coef,
+                    int ld_coef, double sign, double *w, const double *D, int64_t ldd, int ndot, double *partial,
+                    int ld_partial, hipStream_t s);
 int launch_sub(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
 int launch_add_inplace(int64_t n, const double *a, double *out, hipStream_t s);
 int launch_fill(int64_t n, double v, double *out, hipStream_t s);
