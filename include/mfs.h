@@ -212,14 +212,16 @@ typedef struct {
 
 /* Builds a plan: uploads geometry, assembles S_L (MFS_MOBILITY) or S^(kk)
  * (MFS_RESISTANCE) for every (shape, kind) in FP64 on the device, factors it
- * (FP64 SVD), stores U^T and W = V Sigma^{-1} in FP64 and FP32, and the
- * per-body Gram inverses.  Synchronous.  Below, "S_L" stands for the plan's
+ * (FP64 SVD, or QR with MFS_FACTOR_QR), stores U^T and W = V Sigma^{-1}
+ * (Q^T and R^-1) in FP64 and FP32, and the per-body Gram inverses.  Synchronous.  Below, "S_L" stands for the plan's
  * one-body block, and the projection (I - L) is the identity in a
  * MFS_RESISTANCE plan. */
 int mfs_plan_create(mfs_plan *out, const mfs_plan_desc *desc, void *stream);
 int mfs_plan_destroy(mfs_plan plan);
 /* Totals of the three vector layouts above, and the smallest
- * sigma_min/sigma_max over the plan's factors ([host] outputs, any may be NULL). */
+ * sigma_min/sigma_max over the plan's factors (MFS_FACTOR_QR plans: the
+ * smallest 1/(||R||_F ||R^-1||_F), a lower bound of it) ([host] outputs, any
+ * may be NULL). */
 int mfs_plan_sizes(mfs_plan plan, int64_t *n_gamma, int64_t *n_lambda, int64_t *n_net,
                    double *min_sigma_ratio);
 /* Moves the plan's bodies: new centres [host][n_body][3] and rotations
