@@ -164,7 +164,19 @@ def cpu_baseline(wl, budget_s: float = 15.0):
                   f"rows (all {len(pr.bodies)} pseudo-inverse blocks + those rows' off-body pair sums), "
                   f"{dt:.1f} s")
     return dict(value=pairs / dt / 1e9, unit="Ginteractions/s", cores=O.oracle_threads(), kind="oracle",
-                sample=sample + "; off-body pairs per second of that work", seconds=dt)
+                sample=sample + "; off-body pairs per second of that work", seconds=dt,
+                host_cpu=_cpu_model(), host_logical_cpus=os.cpu_count())
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def two_way_bench(args, mfs, torch, np):
