@@ -99,3 +99,45 @@ def test_bodies_of_different_sizes_in_one_system():
         assert info["status"] == mfs.MFS_OK
         assert rel_inf(out.cpu().numpy(), sol["out"]) <= bar
         plan.close()
+
+
+def test_many_systems_and_one_iteration():
+    """300 two-body systems (more systems than one block of the least-squares
+    kernels holds), Stokes and Laplace alternating, against the oracle per
+    system; and max_iter = 1, where the solve stops after one iteration with
+    MFS_NOT_CONVERGED and gamma is the one-step GMRES iterate."""
+    mfs = _mfs()
+    n_sys = 300
+    kinds = [W.STOKES if s % 2 == 0 else W.LAPLACE for s in range(n_sys)]
+    parts = [W.small_cluster(2, k, 20, 48, seed=200 + s, axes=(1.0, 1.0, 1.0)) for s, k in enumerate(kinds)]
+    sh = parts[0].shapes[0]
+    centre = np.concatenate([p.centre + 40.0 * s for s, p in enumerate(parts)])
+    rot = np.concatenate([p.rot for p in parts])
+    ptr = np.arange(0, 2 * n_sys + 1, 2)
+    plan = mfs.Plan(mfs.FP64, ptr, kinds, centre, rot, np.zeros(2 * n_sys, np.int32), [sh.src], [sh.trg])
+    net = _dev(np.concatenate([p.net[0].reshape(-1) for p in parts]))
+    out, info = plan.solve(net, tol=1e-10)
+    assert info["status"] == mfs.MFS_OK
+    got = out.cpu().numpy()
+    off = 0
+    for s, p in enumerate(parts):
+        m = 2 * (6 if kinds[s] == W.STOKES else 1)
+        if s % 37 == 0:
+            ref = O.Problem.from_workload(p).solve(p.net[0], tol=1e-12)["out"]
+            assert rel_inf(got[off:off + m], np.asarray(ref).reshape(-1)) <= 1e-8, s
+        off += m
+    # max_iter = 1: one Arnoldi step, x = y_0 v_0 with y_0 = g_0 / R_00
+    b, _ = plan.rhs(net)
+    g1, it1, rr1, st1 = plan.gmres_solve(b, tol=1e-12, max_iter=1)
+    assert st1 == mfs.MFS_NOT_CONVERGED and list(set(it1.tolist())) == [1]
+    Ab = plan.matvec(b, mfs.FP64)
+    # per system, the one-step minimiser of |b - t A b| is t = (Ab . b) / (Ab . Ab): gamma = t b
+    gam = g1.cpu().numpy()
+    bn, Abn = b.cpu().numpy(), Ab.cpu().numpy()
+    for s in range(0, n_sys, 50):
+        n_s = 2 * (3 if kinds[s] == W.STOKES else 1) * sh.trg.shape[0]
+        lo = sum(2 * (3 if kinds[q] == W.STOKES else 1) * sh.trg.shape[0] for q in range(s))
+        seg = slice(lo, lo + n_s)
+        t = float(Abn[seg] @ bn[seg]) / float(Abn[seg] @ Abn[seg])
+        assert np.abs(gam[seg] - t * bn[seg]).max() <= 1e-10 * np.abs(t * bn[seg]).max()
+    plan.close()
