@@ -75,3 +75,35 @@ def test_plan_descriptor_layout_matches_the_header():
     body = re.search(r"typedef struct \{(.*?)\} mfs_plan_desc;", text, flags=re.S).group(1)
     c_fields = re.findall(r"\*?\s*([a-z_0-9]+);", body)
     assert [f[0] for f in mfs.PlanDesc._fields_] == c_fields
+
+
+def test_header_is_plain_c_and_the_layout_matches_the_binding(tmp_path):
+    """A C99 program includes mfs.h, links libmfs.so and calls it (no GPU call):
+    the header is plain C, and the byte offsets of mfs_plan_desc agree with the
+    ctypes descriptor the Python binding passes."""
+    import shutil
+    import subprocess
+    from paper_2409_04215_amd import mfs
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in mfs.PlanDesc._fields_]
+    src = tmp_path / "abi.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"mfs.h\"\n"
+        "int main(void) {\n"
+        "  printf(\"%s\\n\", mfs_version());\n"
+        f"  printf(\"%zu\\n\", sizeof(mfs_plan_desc));\n"
+        + "".join(f"  printf(\"%zu\\n\", offsetof(mfs_plan_desc, {f}));\n" for f in fields)
+        + "  return mfs_plan_destroy(NULL);\n}\n")
+    exe = tmp_path / "abi"
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe),
+                        LIB, f"-Wl,-rpath,{os.path.dirname(LIB)}"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert "gfx950" in r.stdout.splitlines()[0]
+    nums = [int(x) for x in r.stdout.splitlines()[1:]]
+    assert nums[0] == ctypes.sizeof(mfs.PlanDesc)
+    assert nums[1:] == [getattr(mfs.PlanDesc, f).offset for f in fields]
