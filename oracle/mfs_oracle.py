@@ -517,27 +517,34 @@ class Problem:
         return w + out
 
     def velocity_loss_gradient(self, net, tol: float = 1e-12, max_iter: int = 200):
-        """Loss J = sum_k |U^(k)|^2 and dJ/dc^(k) for every centre (bodies move
-        rigidly: every point of body k shifts with c^(k)).
+        """Loss J = sum_k |U^(k)|^2 (Stokes: rigid velocities) or
+        J = sum_k (phi^(k))^2 (Laplace: body potentials), and dJ/dc^(k) for
+        every centre (bodies move rigidly: every point of body k shifts with
+        c^(k)).
 
         J depends on the centres only through the off-diagonal blocks
         S^(kk') (k != k'); S_L, L, L_r and the completion strengths depend on
         positions relative to the own centre only.  With the residual
         R(gamma, c) = A(c) gamma - b(c), the adjoint identity gives
         dJ/dc = -w^T dR/dc, where A^T w = dJ/dgamma and
-        dJ/dgamma = -2 sum_k (S_L^(k)+)^T K_N^(k) U^(k).
+        dJ/dgamma = -2 sum_k (S_L^(k)+)^T K_N^(k) U^(k) (Stokes, U = -K_N^T lambda,
+        eq. (getU)) or -2 sum_k (S_L^(k)+)^T 1 phi^(k) / N (Laplace, phi = -mean
+        alpha, eq. (vkal)).
         dR/dc collects pair terms w_i . G(x_i - y_j) sigma_j over off-body
         pairs, sigma = (I - L) S_L^+ gamma + s_0 (the full strength: the
         self-included right-hand side only adds same-body pairs, which do
         not move relative to each other)."""
-        assert self.kind == STOKES
         sol = self.solve(net, tol=tol, max_iter=max_iter)
-        U = sol["out"]
-        g = np.concatenate([-2.0 * self.pinv_apply_T(k, K_matrix(b.Y, b.centre) @ U[k])
-                            for k, b in enumerate(self.bodies)])
+        U = np.asarray(sol["out"])
+        if self.kind == STOKES:
+            dl = [-2.0 * K_matrix(b.Y, b.centre) @ U[k] for k, b in enumerate(self.bodies)]
+        else:
+            dl = [np.full(b.Y.shape[0], -2.0 * U[k] / b.Y.shape[0]) for k, b in enumerate(self.bodies)]
+        g = np.concatenate([self.pinv_apply_T(k, dl[k]) for k in range(len(self.bodies))])
         w, it_adj, _ = gmres(self.matvec_T, g, tol, max_iter)
-        gx, gy = p2p_grad(self.kind, self.X, self.trg_body, w.reshape(-1, 3), self.Y, self.src_body,
-                          sol["sigma"].reshape(-1, 3), self.mu, True)
+        shape = (-1, 3) if self.kind == STOKES else (-1,)
+        gx, gy = p2p_grad(self.kind, self.X, self.trg_body, w.reshape(shape), self.Y, self.src_body,
+                          sol["sigma"].reshape(shape), self.mu, True)
         grad = np.zeros((len(self.bodies), 3))
         np.add.at(grad, self.trg_body, gx)
         np.add.at(grad, self.src_body, gy)

@@ -109,3 +109,21 @@ def test_gradient_directional_fd_spheres_200():
         print("directional fd", fd, "mixed", ad, "fp64", ad64)
         assert abs(fd - ad64) <= 1e-6 * np.linalg.norm(g64)
         assert abs(fd - ad) <= 1e-5 * np.linalg.norm(g)
+
+
+def test_elastance_gradient_matches_oracle():
+    """Laplace elastance: J = sum_k (phi^(k))^2, dJ/dphi = 2 phi, against the
+    oracle's adjoint gradient (itself pinned by finite differences)."""
+    mfs = _mfs()
+    wl = W.small_cluster(4, W.LAPLACE, 45, 301, seed=34)
+    J_ref, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-8, 1e-5)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
+        g, iters, relres, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+        assert st == mfs.MFS_OK
+        J = float((out * out).sum())
+        e = rel_inf(g.cpu().numpy(), g_ref)
+        print("elastance", prec, "J", J, J_ref, "grad err", e, "adjoint iters", iters)
+        assert abs(J - J_ref) <= 1e-6 * J_ref and e <= bar
+        plan.close()

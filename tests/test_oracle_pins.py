@@ -299,8 +299,11 @@ def test_pair_gradient_matches_finite_differences():
         assert abs((phi(pr.X, Yp) - phi(pr.X, Ym)) / (2 * h) - gy[j, a]) < 1e-7 * max(1, abs(gy[j, a]))
 
 
-def test_velocity_loss_gradient_matches_finite_differences():
-    wl = W.small_cluster(3, W.STOKES, 30, 60, seed=19, axes=(1.0, 1.0, 1.0))
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_velocity_loss_gradient_matches_finite_differences(kind):
+    """dJ/dc of J = sum |U|^2 (Stokes) or sum phi^2 (Laplace) against central
+    differences of whole solves with one centre coordinate moved."""
+    wl = W.small_cluster(3, kind, 30, 60, seed=19, axes=(1.0, 1.0, 1.0))
     F = wl.net[0]
 
     pr = O.Problem.from_workload(wl)
@@ -310,8 +313,8 @@ def test_velocity_loss_gradient_matches_finite_differences():
         cp, cm = wl.centre.copy(), wl.centre.copy()
         cp[k, a] += h
         cm[k, a] -= h
-        Jp = np.sum(O.Problem(W.STOKES, wl.shapes, cp, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
-        Jm = np.sum(O.Problem(W.STOKES, wl.shapes, cm, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
+        Jp = np.sum(O.Problem(kind, wl.shapes, cp, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
+        Jm = np.sum(O.Problem(kind, wl.shapes, cm, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
         fd = (Jp - Jm) / (2 * h)
         assert abs(fd - grad[k, a]) < 1e-6 * np.abs(grad).max(), (k, a, fd, grad[k, a])
 
