@@ -17,7 +17,7 @@ over the stacked output.  Bars (the same as the per-entry-point tests):
   A gamma, A^T w                 1e-10     1e-4   the off-body sums damp the rough part again
   gamma, lambda, sigma (solve)   1e-8      1e-3   FP64 solve at tol 1e-10; mixed at tol 1e-5
   U or phi (solve)               1e-8      1e-5   the outputs the method reports
-  dJ/dc (adjoint, Stokes)        1e-8      1e-5   J = sum |U|^2; FP64 tol 1e-12, mixed tol 1e-8
+  dJ/dc (adjoint)                1e-8      1e-5   J = sum |U|^2 or sum phi^2; FP64 tol 1e-12, mixed tol 1e-8
   resistance / capacitance (Section 2): rhs 1e-13 / 1e-13, S^+ apply and
   A gamma as above, F or q from the solve 1e-8 / 1e-5 (mixed solve at tol 1e-6)
 
@@ -135,16 +135,15 @@ def _rows(kind):
         add("lambda", prec, rel_inf(_np(lam), sol["lam"]))
         plan.close()
 
-    # adjoint gradient of J = sum |U|^2 with respect to the centres
-    if kind == W.STOKES:
-        _, g_ref, _ = pr.velocity_loss_gradient(wl.net[0], tol=1e-12)
-        for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
-            plan = mfs.Plan.from_workload(wl, prec)
-            out, info = plan.solve(net, tol=tol)
-            gc, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
-            assert st == mfs.MFS_OK
-            add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
-            plan.close()
+    # adjoint gradient of J = sum |U|^2 (Stokes) or sum phi^2 (Laplace) with respect to the centres
+    _, g_ref, _ = pr.velocity_loss_gradient(wl.net[0], tol=1e-12)
+    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(net, tol=tol)
+        gc, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+        assert st == mfs.MFS_OK
+        add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
+        plan.close()
     # the Dirichlet formulation (capacitance / resistance, Section 2)
     rp = O.ResistanceProblem.from_workload(wl)
     data = np.random.default_rng(95).standard_normal((wl.n_body, 6) if kind == W.STOKES else wl.n_body)
