@@ -1784,9 +1784,16 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
     if (reps < 1 || reps > 100) return fail(MFS_EINVAL, "reps must be in [1, 100]");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int64_t> src_row(p->src_row), trg_row(p->trg_row);
-    hipEvent_t e0, e1;
-    MFS_HIP_TRY(hipEventCreate(&e0));
-    MFS_HIP_TRY(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (auto x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    MFS_HIP_TRY(hipEventCreate(&ev.e[0]));
+    MFS_HIP_TRY(hipEventCreate(&ev.e[1]));
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     double best = 1e300;
     int btpl = p->tuned_tpl, bmi = p->tuned_min_items;
     const int tpls[2] = {1, 2};
@@ -1825,8 +1832,6 @@ extern "C" int mfs_plan_autotune(mfs_plan p, int32_t prec, int32_t reps, int32_t
             if (status < 0) break;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (status < 0) return status;
     // the fastest shape; among shapes within 1.5% of it (timing noise), the one with the fewest
     // source splits (fewer FP64 slices written and re-read), then the fewest work items
