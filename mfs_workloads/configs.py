@@ -37,7 +37,7 @@ from typing import List
 
 import numpy as np
 
-from .geometry import (ellipsoid_ring_grid, fibonacci_sphere, fibonacci_spheroid, grown_sphere_cluster,
+from .geometry import (compact_sphere_cluster, ellipsoid_ring_grid, fibonacci_sphere, fibonacci_spheroid, grown_sphere_cluster,
                        random_cluster, random_rotation, ring_grid_size, shift_inward)
 
 LAPLACE = 0
@@ -330,3 +330,20 @@ def smooth_vector(wl: Workload, seed: int) -> np.ndarray:
             coef = rng.standard_normal((feats.shape[1], dim))
             parts.append((feats @ coef).reshape(-1))
     return np.concatenate(parts)
+
+
+def elastance_spheres(n_src: int = 969, n_trg: int = 1123, n_body: int = 10, delta: float = 0.1,
+                      seed: int = 0) -> Workload:
+    """The paper's small elastance test (Section 6): n_body unit spheres grown
+    compactly from the origin at minimum gap delta (compact_sphere_cluster),
+    N proxies on the concentric sphere of radius R_p = 0.7 and M collocation
+    points on the surface (N = 969, M = 1123 as in the paper), Fibonacci point
+    sets in place of its spherical designs.  Net charges q ~ N(0, 1) (the paper
+    does not state them)."""
+    g, r = np.random.SeedSequence(7000 + seed).spawn(2)
+    cen = compact_sphere_cluster(np.random.default_rng(g), n_body, delta)
+    q = np.random.default_rng(r).standard_normal(n_body)
+    shape = Shape(axes=np.ones(3), src=fibonacci_sphere(n_src, PROXY_SCALE), trg=fibonacci_sphere(n_trg, 1.0))
+    rot = np.repeat(np.eye(3)[None], n_body, axis=0)
+    return Workload("elastance_spheres", [shape], cen, rot, np.zeros(n_body, np.int32),
+                    np.array([0, n_body], np.int64), np.array([LAPLACE], np.int32), [q])

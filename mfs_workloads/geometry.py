@@ -269,3 +269,27 @@ def grown_sphere_cluster(rng: np.random.Generator, n: int, delta: float, radius:
         grid.setdefault(key, []).append(k)
         k += 1
     return cen
+
+def compact_sphere_cluster(rng: np.random.Generator, n: int, delta: float, radius: float = 1.0) -> np.ndarray:
+    """Centres of n spheres grown from the origin as in the paper's small
+    elastance test (Section 6): the first sphere sits at the origin; each new one
+    is placed along a uniformly random direction u at the smallest distance t
+    from the origin where its surface gap to every placed sphere is at least
+    delta, so the gap to at least one of them is exactly delta.  For a placed
+    centre p the forbidden distances are the roots interval of
+    |t u - p|^2 < (2 radius + delta)^2; t is the smallest t >= 0 outside all of
+    them."""
+    d = 2.0 * radius + delta
+    cen = np.zeros((n, 3))
+    for k in range(1, n):
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        b = cen[:k] @ u
+        disc = b * b - (np.sum(cen[:k] ** 2, axis=1) - d * d)
+        iv = sorted((bi - np.sqrt(di), bi + np.sqrt(di)) for bi, di in zip(b, disc) if di > 0.0)
+        t = 0.0
+        for lo, hi in iv:  # sweep the forbidden intervals in order of their start
+            if lo <= t < hi:
+                t = hi
+        cen[k] = t * u
+    return cen

@@ -1,0 +1,66 @@
+"""The paper's small elastance test (Section 6) at its own sizes on the GPU:
+10 unit spheres grown compactly at delta = 0.1, R_p = 0.7, N = 969, M = 1123,
+GMRES tolerance 1e-8 (values in tests/golden/paper_elastance_spheres.txt).
+
+The oracle's GMRES at tol needs 15 iterations, the paper's count.  The library's
+GMRES aims at tol/2, so the GPU is compared with the oracle run to tol/2 (16):
+* FP64 plan: the same iteration count, potentials within 1e-8, the same maximum
+  surface residual |u - phi| (4000 points per sphere) to 1e-3 of itself.
+* Mixed plan at the same tolerance (FP64 true-residual refinement): potentials
+  within 1e-6, surface residual within 1e-2 of the oracle's maximum.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import mfs_workloads as W
+from oracle import mfs_oracle as O
+from tests._helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _mfs():
+    from paper_2409_04215_amd import mfs
+    return mfs
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+def _ref():
+    vals = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_elastance_spheres.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+@pytest.mark.timeout(300)
+def test_paper_elastance_example_on_gpu():
+    mfs = _mfs()
+    ref = _ref()
+    wl = W.elastance_spheres(int(ref["N"]), int(ref["M"]), n_body=int(ref["P"]), delta=ref["delta"])
+    tol = ref["gmres_tol"]
+    pr = O.Problem.from_workload(wl)
+    assert abs(pr.solve(wl.net[0], tol=tol)["iters"] - ref["gmres_iterations"]) <= 1
+    sol = pr.solve(wl.net[0], tol=tol / 2)
+    test = W.fibonacci_sphere(4000, 1.0)
+    eps_ref = pr.surface_residual(sol["sigma"], sol["out"], test).max()
+    for prec, bar, eps_bar in ((mfs.FP64, 1e-8, 1e-3), (mfs.MIXED, 1e-6, 1e-2)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(wl.net[0]), tol=tol)
+        _, sigma = plan.extract(info["gamma"], info["s0"], want_sigma=True)
+        eps = plan.surface_residual(sigma, out, test).cpu().numpy().max()
+        e = rel_inf(out.cpu().numpy(), sol["out"])
+        print("paper elastance", prec, "iters", info["iters"], "oracle iters", sol["iters"], "phi err", e,
+              "max |u - phi|", eps, "oracle", eps_ref)
+        assert info["status"] == mfs.MFS_OK and e <= bar
+        assert abs(eps - eps_ref) <= eps_bar * eps_ref
+        if prec == mfs.FP64:
+            assert info["iters"][0] == sol["iters"]
+        plan.close()
