@@ -22,3 +22,38 @@ def structure(wl):
 
 def net_flat(wl):
     return np.concatenate([np.asarray(n, np.float64).reshape(-1) for n in wl.net])
+
+
+def stimson_jeffery_lambda(d: float, a: float = 1.0, terms: int = 400) -> float:
+    """Exact drag factor of two equal spheres (radius a, centre distance d)
+    translating with equal velocity U along their line of centres, from the
+    bispherical-coordinate series of Stimson & Jeffery (Proc. R. Soc. A 111,
+    1926; also Happel & Brenner, Low Reynolds Number Hydrodynamics, Sec. 6.3):
+    the force on each sphere is 6 pi mu a U lambda with, for cosh(alpha) = d/(2a),
+
+      lambda = (4/3) sinh(alpha) sum_{n>=1} n(n+1) / ((2n-1)(2n+3)) *
+               [1 - (4 sinh^2((n+1/2) alpha) - (2n+1)^2 sinh^2(alpha))
+                    / (2 sinh((2n+1) alpha) + (2n+1) sinh(2 alpha))].
+
+    The terms fall like exp(-2 n alpha); 400 of them reach FP64 for gaps down
+    to ~1e-3 a."""
+    al = np.arccosh(d / (2.0 * a))
+    s = 0.0
+    for n in range(1, terms + 1):
+        num = 4.0 * np.sinh((n + 0.5) * al) ** 2 - (2 * n + 1) ** 2 * np.sinh(al) ** 2
+        den = 2.0 * np.sinh((2 * n + 1) * al) + (2 * n + 1) * np.sinh(2.0 * al)
+        term = n * (n + 1) / ((2 * n - 1) * (2 * n + 3)) * (1.0 - num / den)
+        s += term
+        if n > 10 and abs(term) < 1e-18 * abs(s):
+            break
+    return 4.0 / 3.0 * np.sinh(al) * s
+
+
+def two_sphere_workload(W, delta: float, n_src: int, n_trg: int, proxy_radius: float = 0.7):
+    """Two unit spheres on the x axis, gap delta, equal unit forces along x."""
+    shape = W.Shape(axes=np.ones(3), src=W.fibonacci_sphere(n_src, proxy_radius), trg=W.fibonacci_sphere(n_trg, 1.0))
+    cen = np.array([[0.0, 0.0, 0.0], [2.0 + delta, 0.0, 0.0]])
+    rot = np.repeat(np.eye(3)[None], 2, axis=0)
+    net = np.array([[1.0, 0, 0, 0, 0, 0], [1.0, 0, 0, 0, 0, 0]])
+    return W.Workload("two_spheres", [shape], cen, rot, np.zeros(2, np.int32), np.array([0, 2], np.int64),
+                      np.array([W.STOKES], np.int32), [net])

@@ -64,3 +64,23 @@ def test_paper_elastance_example_on_gpu():
         if prec == mfs.FP64:
             assert info["iters"][0] == sol["iters"]
         plan.close()
+
+
+@pytest.mark.parametrize("delta", [0.2, 0.5])
+def test_two_spheres_exact_on_gpu(delta):
+    """Two unit spheres, equal forces along the line of centres (the paper's
+    two-sphere comparison setting, Section 7): GPU velocities against the exact
+    Stimson-Jeffery solution.  N = 800, M = 1600: FP64 within 1e-8 (the MFS
+    discretisation error here is 4e-10), mixed at tol 1e-7 within 1e-6."""
+    from tests._helpers import stimson_jeffery_lambda, two_sphere_workload
+    mfs = _mfs()
+    exact = 1.0 / (6.0 * np.pi * stimson_jeffery_lambda(2.0 + delta))
+    wl = two_sphere_workload(W, delta, 800, 1600)
+    for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-7, 1e-6)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(wl.net[0]), tol=tol)
+        U = out.cpu().numpy().reshape(2, 6)
+        err = np.abs(U[:, 0] - exact).max() / exact
+        print("two spheres", delta, prec, "U_x", U[:, 0], "exact", exact, "rel err", err)
+        assert info["status"] == mfs.MFS_OK and err <= bar
+        plan.close()

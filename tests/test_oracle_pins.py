@@ -603,3 +603,26 @@ def test_paper_elastance_example():
     assert all(abs(i - ref["gmres_iterations"]) <= 1 for i in its)
     assert res[0] > 5 * res[1] > 25 * res[2]
     assert res[2] <= 10.0 ** (1 - ref["surface_residual_digits"])
+
+
+# ---------------------------------------------------------------------------
+# two spheres: the exact Stimson-Jeffery solution (the two-sphere setting of
+# the paper's comparison with spherical-harmonic solvers, Section 7)
+# ---------------------------------------------------------------------------
+
+def test_two_spheres_along_the_line_of_centres_exact():
+    """Two unit spheres, gap delta, equal forces along the line of centres: the
+    mobility solve gives U = F / (6 pi mu a lambda) with lambda from the
+    Stimson-Jeffery series (tests/_helpers.py), no rotation, and the error falls
+    with N (the paper reports ~1e-6 near N = 300 at delta = 0.2)."""
+    from tests._helpers import stimson_jeffery_lambda, two_sphere_workload
+    for delta in (0.2, 0.5):
+        exact = 1.0 / (6.0 * np.pi * stimson_jeffery_lambda(2.0 + delta))
+        errs = []
+        for n in (300, 800):
+            wl = two_sphere_workload(W, delta, n, 2 * n)
+            U = O.Problem.from_workload(wl).solve(wl.net[0], tol=1e-13)["out"]
+            errs.append(max(abs(U[0, 0] - exact), abs(U[1, 0] - exact)) / exact)
+            assert np.abs(U[:, 1:3]).max() < 1e-6 * exact and np.abs(U[:, 3:]).max() < 1e-6 * exact
+        print("delta", delta, "relative error at N = 300, 800:", errs)
+        assert errs[0] < 1e-6 and errs[1] < 1e-8 and errs[1] < errs[0] / 10
