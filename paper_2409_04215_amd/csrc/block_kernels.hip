@@ -5,8 +5,9 @@
 //    factor are one GEMM: the columns are the bodies' vectors rotated into the
 //    shape frame (Remark "congruent": lambda = R V Sigma^+ U^T R^T gamma).
 //    GEMMs run on the matrix cores: v_mfma_f32_32x32x2_f32 (mixed) or
-//    v_mfma_f64_16x16x4_f64 (FP64), LDS-staged 64x64 output tiles, one
-//    launch for every (factor, body-column) tile of every shape.
+//    v_mfma_f64_16x16x4_f64 (FP64), one 32x32 output tile per wave loaded
+//    straight into registers, one launch for every (factor, body-column)
+//    tile of every shape.
 //  * Projection (I - L): constants for Laplace (Section 3.1); rigid motions
 //    L = K_N (K_N^T K_N)^{-1} K_N^T for Stokes (Section 3.2).  Never formed:
 //    a 6-vector reduction w = K_N^T v, z = G^{-1} w, v - K_N z.  FP64.
