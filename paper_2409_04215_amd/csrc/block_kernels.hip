@@ -28,70 +28,188 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // A_g row-major (M x K, lda = K) in a factor pool; B and C columns are
 // contiguous vectors at per-column element offsets.
 //
-// One wave computes one 32 x 32 output tile over a K range.  Fragments are
-// loaded straight from global memory into registers (no LDS): the order in
-// which the K index is visited is permuted per lane so that every lane reads
-// contiguous runs of its own A row and B column (any bijection of K that A
-// and B share leaves the product unchanged).
-//  * f32, v_mfma_f32_32x32x2f32: lane l holds A[l%32][k] and B[k][l%32];
-//    lanes 0-31 walk k in [k0, k0+32), lanes 32-63 in [k0+32, k0+64).
+// One workgroup computes one 32 x 32 output tile over a K range; its four
+// waves take consecutive quarters of that range and add their partial tiles
+// in LDS in wave order.  Each wave streams its quarter through its own LDS
+// stage, one 128-byte run of K at a time (32 floats or 16 doubles):
+//  * global -> registers, coalesced: lane l fetches the 16-byte piece l%8 of
+//    the run of A row (and B column) l/8 + 8i, i < 4, so one load instruction
+//    covers whole 128-byte lines of eight rows; the next run is fetched while
+//    the current one is multiplied;
+//  * registers -> LDS (rows padded by 16 bytes against bank conflicts), then
+//    LDS -> MFMA fragments.  The stage belongs to one wave, whose LDS accesses
+//    complete in order, so no workgroup barrier is needed inside the loop.
+// The K index is permuted per lane inside a run (any bijection of K that A
+// and B share leaves the product unchanged):
+//  * f32, v_mfma_f32_32x32x2f32: lane l holds A[l%32][k] and B[k][l%32] for
+//    k = 16 (l/32) + t, t < 16, one MFMA per t;
 //  * f64, v_mfma_f64_16x16x4f64 (2 x 2 blocks of 16 x 16): lane l holds
-//    A[l%16][k] and B[k][l%16]; lane group l/16 walks 16 consecutive k.
-// A K range is split across waves when there are few output tiles; split
-// slices land in a partial buffer that a second kernel sums in a fixed order.
+//    A[l%16][k] and B[k][l%16] for k = 4 (l/16) + t, t < 4.
+// Tiles are handed out XCD-aware: workgroup b runs on XCD b % 8 and takes
+// tile (b % 8) * per_xcd + b / 8, so the column tiles of one (row tile, K
+// range), which are consecutive in the tile list, run on one XCD and fetch
+// their shared rows of A into its L2 once.  A K range is split over several
+// tiles when there are few output tiles; split slices land in a partial
+// buffer that a second kernel sums in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int KT = 64;  // K per register tile
+constexpr int RUN_BYTES = 128;                      // one K run per LDS stage
+constexpr int ROW_BYTES = RUN_BYTES + 16;           // padded LDS row
+constexpr int STAGE_BYTES = 2 * 32 * ROW_BYTES;     // A and B runs of 32 rows / columns
 
-template <class T, int N>
-__device__ __forceinline__ void load_run(const T *__restrict__ p, int k, int K, bool ok, bool vec, T (&v)[N]) {
-    // v[t] = p[k + t] for k + t < K (else 0); p is a row or column start
-    if (ok && vec && k + N <= K) {
+template <class T>
+struct Piece {  // 16 bytes of a run
+    static constexpr int E = 16 / sizeof(T);
+    T v[E];
+};
+
+// lane's piece of a run starting at k0 of one row (or column) p; zero past ke or when !ok
+template <class T>
+__device__ __forceinline__ Piece<T> load_piece(const T *__restrict__ p, int k, int ke, bool ok, bool vec) {
+    constexpr int E = Piece<T>::E;
+    Piece<T> r;
+    if (ok && vec && k + E <= ke) {
         if constexpr (sizeof(T) == 4) {
-#pragma unroll
-            for (int t = 0; t < N; t += 4) {
-                const float4 q = *reinterpret_cast<const float4 *>(p + k + t);
-                v[t] = q.x; v[t + 1] = q.y; v[t + 2] = q.z; v[t + 3] = q.w;
-            }
+            const float4 q = *reinterpret_cast<const float4 *>(p + k);
+            r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
         } else {
-#pragma unroll
-            for (int t = 0; t < N; t += 2) {
-                const double2 q = *reinterpret_cast<const double2 *>(p + k + t);
-                v[t] = q.x; v[t + 1] = q.y;
-            }
+            const double2 q = *reinterpret_cast<const double2 *>(p + k);
+            r.v[0] = q.x; r.v[1] = q.y;
         }
     } else {
 #pragma unroll
-        for (int t = 0; t < N; ++t) v[t] = (ok && k + t < K) ? p[k + t] : T(0);
+        for (int e = 0; e < E; ++e) r.v[e] = (ok && k + e < ke) ? p[k + e] : T(0);
     }
+    return r;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, const GemmTile *__restrict__ tiles,
+__global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, const GemmTile *__restrict__ tiles,
                                                    const GemmGroup *__restrict__ groups, const T *__restrict__ Apool,
                                                    const T *__restrict__ B, const int64_t *__restrict__ b_col_off,
                                                    T *__restrict__ C, const int64_t *__restrict__ c_col_off,
                                                    T *__restrict__ partial, int64_t part_col_stride,
                                                    int64_t part_split_stride, int vec_ok) {
-    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (task >= n_tiles) return;
+    constexpr int E = Piece<T>::E;                  // elements per 16-byte piece
+    constexpr int KR = RUN_BYTES / sizeof(T);       // K per run: 32 floats or 16 doubles
+    constexpr int LD = ROW_BYTES / sizeof(T);       // LDS row stride in elements
+    __shared__ __align__(16) char smem[4][STAGE_BYTES];
+    const int task = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (task >= n_tiles) return;  // uniform over the workgroup
     const GemmTile tl = tiles[task];
     const GemmGroup g = groups[tl.group];
     const T *A = Apool + g.a_off;
-    const int lane = threadIdx.x & 63;
-    const bool vec = vec_ok && (g.K % (sizeof(T) == 4 ? 4 : 2)) == 0;
-    if constexpr (sizeof(T) == 4) {
-        const int i = tl.m0 + (lane & 31), j = tl.n0 + (lane & 31), h = lane >> 5;
-        const bool a_ok = i < g.M, b_ok = j < g.ncol;
-        const T *arow = A + (int64_t)(a_ok ? i : 0) * g.K;
-        const T *bcol = B + b_col_off[g.col_begin + (b_ok ? j : 0)];
-        floatx16 acc = {};
-        for (int k0 = tl.k0; k0 < tl.k1; k0 += KT) {
-            float av[32], bv[32];
-            load_run<float, 32>(arow, k0 + 32 * h, tl.k1, a_ok, vec, av);
-            load_run<float, 32>(bcol, k0 + 32 * h, tl.k1, b_ok, vec, bv);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = (tl.k1 - tl.k0 + 4 * KR - 1) / (4 * KR) * KR;
+    const int kb = min(tl.k1, tl.k0 + wave * kq), ke = min(tl.k1, kb + kq);
+    const bool vec = vec_ok && (g.K % E) == 0;
+    T *As = reinterpret_cast<T *>(smem[wave]);
+    T *Bs = As + 32 * LD;
+
+    // this lane's rows of A and columns of B for the global loads
+    const int pc = lane & 7, pr = lane >> 3;
+    const T *ap[4];
+    const T *bp[4];
+    bool aok[4], bok[4];
 #pragma unroll
-            for (int t = 0; t < 32; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+        const int r = tl.m0 + pr + 8 * i, c = tl.n0 + pr + 8 * i;
+        aok[i] = r < g.M;
+        bok[i] = c < g.ncol;
+        ap[i] = A + (int64_t)(aok[i] ? r : 0) * g.K;
+        bp[i] = B + b_col_off[g.col_begin + (bok[i] ? c : 0)];
+    }
+    Piece<T> ga[4], gb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ga[i] = load_piece<T>(ap[i], k0 + E * pc, ke, aok[i], vec);
+            gb[i] = load_piece<T>(bp[i], k0 + E * pc, ke, bok[i], vec);
         }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<Piece<T> *>(As + (pr + 8 * i) * LD + E * pc) = ga[i];
+            *reinterpret_cast<Piece<T> *>(Bs + (pr + 8 * i) * LD + E * pc) = gb[i];
+        }
+    };
+
+    T val[16];
+    if (kb < ke) fetch(kb);
+    if constexpr (sizeof(T) == 4) {
+        const int c = lane & 31, h = lane >> 5;
+        floatx16 acc = {};
+        for (int k0 = kb; k0 < ke; k0 += KR) {
+            stage();
+            wave_lds_sync();
+            if (k0 + KR < ke) fetch(k0 + KR);
+            float av[16], bv[16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 x = *reinterpret_cast<const float4 *>(As + c * LD + 16 * h + 4 * j);
+                const float4 y = *reinterpret_cast<const float4 *>(Bs + c * LD + 16 * h + 4 * j);
+                av[4 * j] = x.x; av[4 * j + 1] = x.y; av[4 * j + 2] = x.z; av[4 * j + 3] = x.w;
+                bv[4 * j] = y.x; bv[4 * j + 1] = y.y; bv[4 * j + 2] = y.z; bv[4 * j + 3] = y.w;
+            }
+            wave_lds_sync();  // the next run's stores follow these reads
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) val[r] = acc[r];
+    } else {
+        const int q = lane >> 4, c16 = lane & 15;
+        doublex4 acc[2][2] = {};
+        for (int k0 = kb; k0 < ke; k0 += KR) {
+            stage();
+            wave_lds_sync();
+            if (k0 + KR < ke) fetch(k0 + KR);
+            double av[2][4], bv[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double2 x = *reinterpret_cast<const double2 *>(As + (16 * u + c16) * LD + 4 * q + 2 * j);
+                    const double2 y = *reinterpret_cast<const double2 *>(Bs + (16 * u + c16) * LD + 4 * q + 2 * j);
+                    av[u][2 * j] = x.x; av[u][2 * j + 1] = x.y;
+                    bv[u][2 * j] = y.x; bv[u][2 * j + 1] = y.y;
+                }
+            wave_lds_sync();
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int w = 0; w < 2; ++w)
+                        acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[w][t], acc[u][w], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int w = 0; w < 2; ++w)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) val[(2 * u + w) * 4 + r] = acc[u][w][r];
+    }
+    // partial tiles of waves 1-3 through their own stages, added to wave 0's in wave order
+    T *red = reinterpret_cast<T *>(smem[wave]);
+    if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[r * 64 + lane] = val[r];
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+        const T *o = reinterpret_cast<const T *>(smem[w]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) val[r] += o[r * 64 + lane];
+    }
+    if constexpr (sizeof(T) == 4) {
         // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
         const int col = tl.n0 + (lane & 31);
         if (col < g.ncol) {
@@ -100,39 +218,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, const GemmTile *
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = tl.m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                if (row < g.M) out[row] = acc[r];
+                if (row < g.M) out[row] = val[r];
             }
         }
     } else {
-        const int q = lane >> 4, c16 = lane & 15;
-        const T *arow[2];
-        const T *bcol[2];
-        bool a_ok[2], b_ok[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int i = tl.m0 + 16 * u + c16, j = tl.n0 + 16 * u + c16;
-            a_ok[u] = i < g.M;
-            b_ok[u] = j < g.ncol;
-            arow[u] = A + (int64_t)(a_ok[u] ? i : 0) * g.K;
-            bcol[u] = B + b_col_off[g.col_begin + (b_ok[u] ? j : 0)];
-        }
-        doublex4 acc[2][2] = {};
-        for (int k0 = tl.k0; k0 < tl.k1; k0 += KT) {
-            double av[2][16], bv[2][16];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                load_run<double, 16>(arow[u], k0 + 16 * q, tl.k1, a_ok[u], vec, av[u]);
-                load_run<double, 16>(bcol[u], k0 + 16 * q, tl.k1, b_ok[u], vec, bv[u]);
-            }
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int w = 0; w < 2; ++w)
-                        acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[w][t], acc[u][w], 0, 0, 0);
-        }
         // D layout (16x16x4 f64, measured on gfx950): lane l, reg r -> row l/16 + 4 r, col l%16
+        const int q = lane >> 4, c16 = lane & 15;
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
             const int col = tl.n0 + 16 * w + c16;
@@ -144,7 +235,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, const GemmTile *
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = tl.m0 + 16 * u + q + 4 * r;
-                    if (row < g.M) out[row] = acc[u][w][r];
+                    if (row < g.M) out[row] = val[(2 * u + w) * 4 + r];
                 }
         }
     }
@@ -620,7 +711,8 @@ int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, con
                     const int64_t *c_col_off, float *partial, hipStream_t s) {
     if (G.n_tiles == 0) return MFS_OK;
     float *part = G.n_split > 1 ? partial : nullptr;
-    gemm_kernel<float><<<(G.n_tiles + 3) / 4, 256, 0, s>>>(G.n_tiles, G.tiles, G.groups, Apool, B, b_col_off, C,
+    const int per_xcd = (G.n_tiles + 7) / 8;
+    gemm_kernel<float><<<8 * per_xcd, 256, 0, s>>>(G.n_tiles, per_xcd, G.tiles, G.groups, Apool, B, b_col_off, C,
                                                           c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
     if (part) {
@@ -635,7 +727,8 @@ int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, c
                     const int64_t *c_col_off, double *partial, hipStream_t s) {
     if (G.n_tiles == 0) return MFS_OK;
     double *part = G.n_split > 1 ? partial : nullptr;
-    gemm_kernel<double><<<(G.n_tiles + 3) / 4, 256, 0, s>>>(G.n_tiles, G.tiles, G.groups, Apool, B, b_col_off, C,
+    const int per_xcd = (G.n_tiles + 7) / 8;
+    gemm_kernel<double><<<8 * per_xcd, 256, 0, s>>>(G.n_tiles, per_xcd, G.tiles, G.groups, Apool, B, b_col_off, C,
                                                             c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
     if (part) {

@@ -569,8 +569,10 @@ void rotate_gram(const double *G0i, const double *R, double *Gi) {
         }
 }
 
-// Work tables of one grouped GEMM: tiles of 32 x 32 outputs, K split into
-// n_split ranges when there are too few tiles to fill the device.
+// Work tables of one grouped GEMM: tiles of 32 x 32 outputs (one workgroup of
+// four waves each), K split into n_split ranges of at least 512 when there are
+// fewer than 1024 tiles (the fastest of the settings timed at 100 and 1000
+// bodies).
 int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &groups,
                       const std::vector<int32_t> &col_group, const std::vector<int64_t> &b_col_off, hipStream_t s) {
     int64_t tiles32 = 0, kmax = 0, mmax = 0;
@@ -579,14 +581,14 @@ int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &g
         kmax = std::max<int64_t>(kmax, g.K);
         mmax = std::max<int64_t>(mmax, g.M);
     }
-    const int64_t target = 2048;
-    int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((target + tiles32 - 1) / tiles32, (kmax + 255) / 256));
+    const int64_t target = 1024, kmin = 512;
+    int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((target + tiles32 - 1) / tiles32, (kmax + kmin - 1) / kmin));
     std::vector<GemmTile> tiles;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const GemmGroup &g = groups[gi];
         const int kchunk = (int)(((g.K + n_split - 1) / n_split + 63) / 64 * 64);
-        // column tiles innermost: the four waves of a workgroup (consecutive tiles) then hold
-        // the same rows and K range of A, which the CU fetches once for all of them
+        // column tiles innermost: consecutive tiles, which the kernel places on one XCD,
+        // then read the same rows and K range of A
         for (int m0 = 0; m0 < g.M; m0 += 32)
             for (int sp = 0; sp < n_split; ++sp)
                 for (int n0 = 0; n0 < g.ncol; n0 += 32) {
