@@ -43,6 +43,22 @@ __device__ __forceinline__ void chunk_dots(const VecChunk ch, const double *V, i
     }
 }
 
+// sum_i V[i][n] cf[i], i < nvec, added in order of i; loads issued DOT_GROUP at a time
+__device__ __forceinline__ double combine(const double *__restrict__ V, int64_t ldv, int nvec,
+                                          const double *__restrict__ cf, int64_t n) {
+    double acc = 0.0;
+    int i = 0;
+    for (; i + DOT_GROUP <= nvec; i += DOT_GROUP) {
+        double v[DOT_GROUP];
+#pragma unroll
+        for (int q = 0; q < DOT_GROUP; ++q) v[q] = V[(int64_t)(i + q) * ldv + n];
+#pragma unroll
+        for (int q = 0; q < DOT_GROUP; ++q) acc += v[q] * cf[i + q];
+    }
+    for (; i < nvec; ++i) acc += V[(int64_t)i * ldv + n] * cf[i];
+    return acc;
+}
+
 // partial[c][i] = sum_{n in chunk c} V[i][n] w[n], i < nvec
 __global__ __launch_bounds__(256) void multi_dot_kernel(const VecChunk *__restrict__ chunks, const double *__restrict__ V,
                                                         int64_t ldv, int nvec, const double *__restrict__ w,
@@ -61,11 +77,7 @@ __global__ __launch_bounds__(256) void axpy_dot_kernel(const VecChunk *__restric
     __shared__ double sh[4][DOT_GROUP];
     const VecChunk ch = chunks[blockIdx.x];
     const double *cf = coef + (int64_t)ch.sys * ld_coef;
-    for (int64_t n = ch.begin + threadIdx.x; n < ch.end; n += 256) {
-        double acc = 0.0;
-        for (int i = 0; i < nvec; ++i) acc += V[(int64_t)i * ldv + n] * cf[i];
-        w[n] += sign * acc;
-    }
+    for (int64_t n = ch.begin + threadIdx.x; n < ch.end; n += 256) w[n] += sign * combine(V, ldv, nvec, cf, n);
     chunk_dots(ch, D, ldd, ndot, w, partial + (int64_t)blockIdx.x * ld_partial, sh);
 }
 
@@ -90,11 +102,7 @@ __global__ void multi_axpy_kernel(const VecChunk *__restrict__ chunks, const dou
                                   const double *__restrict__ coef, int ld_coef, double sign, double *__restrict__ w) {
     const VecChunk ch = chunks[blockIdx.x];
     const double *cf = coef + (int64_t)ch.sys * ld_coef;
-    for (int64_t n = ch.begin + threadIdx.x; n < ch.end; n += blockDim.x) {
-        double acc = 0.0;
-        for (int i = 0; i < nvec; ++i) acc += V[(int64_t)i * ldv + n] * cf[i];
-        w[n] += sign * acc;
-    }
+    for (int64_t n = ch.begin + threadIdx.x; n < ch.end; n += blockDim.x) w[n] += sign * combine(V, ldv, nvec, cf, n);
 }
 
 // out[n] = w[n] * scale[sys(n) * ld_scale]
