@@ -57,7 +57,7 @@ constexpr int ROW_BYTES = RUN_BYTES + 16;           // padded LDS row
 constexpr int STAGE_BYTES = 2 * 32 * ROW_BYTES;     // A and B runs of 32 rows / columns
 
 template <class T>
-struct Piece {  // 16 bytes of a run
+struct __align__(16) Piece {  // 16 bytes of a run
     static constexpr int E = 16 / sizeof(T);
     T v[E];
 };
@@ -126,17 +126,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
     }
     Piece<T> ga[4], gb[4];
     auto fetch = [&](int k0) {
+        if (vec && k0 + KR <= ke) {
+            // the whole run lies inside K (a wave-uniform test): unconditional 16-byte loads;
+            // rows and columns past the end read row / column 0 and are zeroed by stage(),
+            // so nothing waits for these loads before the multiplications that follow
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ga[i] = load_piece<T>(ap[i], k0 + E * pc, ke, aok[i], vec);
-            gb[i] = load_piece<T>(bp[i], k0 + E * pc, ke, bok[i], vec);
+            for (int i = 0; i < 4; ++i) {
+                ga[i] = *reinterpret_cast<const Piece<T> *>(ap[i] + k0 + E * pc);
+                gb[i] = *reinterpret_cast<const Piece<T> *>(bp[i] + k0 + E * pc);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ga[i] = load_piece<T>(ap[i], k0 + E * pc, ke, aok[i], vec);
+                gb[i] = load_piece<T>(bp[i], k0 + E * pc, ke, bok[i], vec);
+            }
         }
     };
     auto stage = [&]() {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            *reinterpret_cast<Piece<T> *>(As + (pr + 8 * i) * LD + E * pc) = ga[i];
-            *reinterpret_cast<Piece<T> *>(Bs + (pr + 8 * i) * LD + E * pc) = gb[i];
+            Piece<T> a = ga[i], b = gb[i];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                a.v[e] = aok[i] ? a.v[e] : T(0);
+                b.v[e] = bok[i] ? b.v[e] : T(0);
+            }
+            *reinterpret_cast<Piece<T> *>(As + (pr + 8 * i) * LD + E * pc) = a;
+            *reinterpret_cast<Piece<T> *>(Bs + (pr + 8 * i) * LD + E * pc) = b;
         }
     };
 
