@@ -1509,6 +1509,7 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
     for (int sy = 0; sy < S; ++sy) counts[sy] += act[sy];  // the matvec of iteration 0
     int done = 0;                                          // iterations enqueued
     bool empty_tail = false;  // the last enqueued iteration found no live system
+    std::vector<double> prev_est(S, 0.0);                  // estimates after the previous status read
     for (int j = 0; j < max_iter; ++j) {
         MFS_TRY(apply_A(p, A, V + (int64_t)j * n, w, prec, s));
         // classical Gram-Schmidt, twice: dots, then (axpy + the next dots) twice, the last
@@ -1564,6 +1565,29 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         // is already enqueued, with lag 0 it is enqueued next unless the capacity ends here
         if (lag == 1 || q + 1 < max_iter)
             for (int sy = 0; sy < S; ++sy) counts[sy] += lv[sy] & 1;
+        // End in sight: when every live system's estimate, carried one iteration further by its
+        // last reduction factor, is within twice its target, wait for iteration q + 1 (already
+        // enqueued) before enqueueing q + 2.  If q + 1 ends the solve, no empty iteration
+        // follows it; otherwise the GPU idles only while the host enqueues q + 2.
+        if (lag == 1) {
+            const double *es = slot_est(q);
+            bool near = true;
+            for (int sy = 0; sy < S; ++sy) {
+                if (!(lv[sy] & 1)) continue;
+                const double e = es[sy], e0 = prev_est[sy];
+                near = near && e0 > 0.0 && std::isfinite(e) && e * (e / e0) <= 2.0 * target[sy];
+            }
+            for (int sy = 0; sy < S; ++sy) prev_est[sy] = es[sy];
+            if (near) {
+                MFS_HIP_TRY(hipEventSynchronize(p->stat_ev[(q + 1) % mfs_plan_s::STAT_SLOTS]));
+                if (!slot_err(q + 1)) {  // an error is reported by the regular read of q + 1
+                    const int32_t *l2 = slot_flag(q + 1);
+                    int live2 = 0;
+                    for (int sy = 0; sy < S; ++sy) live2 += l2[sy] & 1;
+                    if (live2 == 0) break;
+                }
+            }
+        }
     }
     // drain, then the final status and x += V y with y from the device back substitution
     MFS_HIP_TRY(hipStreamSynchronize(s));
