@@ -81,20 +81,27 @@ __global__ __launch_bounds__(256) void axpy_dot_kernel(const VecChunk *__restric
     chunk_dots(ch, D, ldd, ndot, w, partial + (int64_t)blockIdx.x * ld_partial, sh);
 }
 
-// out[s][i] = sum over chunks of system s of partial[c][i]; one block per (i, s),
-// threads stride over the chunks, then a fixed-order tree reduction.
-__global__ __launch_bounds__(256) void reduce_sys_kernel(const int32_t *__restrict__ sys_chunk_ptr,
-                                                         const double *__restrict__ partial, int ld_partial,
-                                                         double *__restrict__ out, int ld_out) {
-    __shared__ double sh[4];
-    const int i = blockIdx.x, s = blockIdx.y;
+// sum over the chunks of system s of partial[c][i], by a workgroup of 256 threads: threads
+// stride over the chunks, then a fixed-order tree reduction; the result is valid in thread 0
+__device__ __forceinline__ double sys_sum(const int32_t *__restrict__ sys_chunk_ptr, const double *__restrict__ partial,
+                                          int ld_partial, int i, int s, double *sh) {
     double acc = 0.0;
     for (int c = sys_chunk_ptr[s] + threadIdx.x; c < sys_chunk_ptr[s + 1]; c += 256)
         acc += partial[(int64_t)c * ld_partial + i];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) out[(int64_t)s * ld_out + i] = sh[0] + sh[1] + sh[2] + sh[3];
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// out[s][i] = sum over chunks of system s of partial[c][i]; one block per (i, s)
+__global__ __launch_bounds__(256) void reduce_sys_kernel(const int32_t *__restrict__ sys_chunk_ptr,
+                                                         const double *__restrict__ partial, int ld_partial,
+                                                         double *__restrict__ out, int ld_out) {
+    __shared__ double sh[4];
+    const int i = blockIdx.x, s = blockIdx.y;
+    const double v = sys_sum(sys_chunk_ptr, partial, ld_partial, i, s, sh);
+    if (threadIdx.x == 0) out[(int64_t)s * ld_out + i] = v;
 }
 
 // w[n] += sign * sum_i V[i][n] coef[sys(n)][i]
@@ -200,10 +207,19 @@ __device__ int givens_column(const GivensState &st, int j, int sy) {
 // holds the solution), or at an exact breakdown (rho = 0: the solution lies in the first
 // j columns).  A non-finite column stops the system and flags it.  Every system's estimate
 // and flags go to the status block of the iteration.
-__global__ void givens_step_kernel(GivensState st, int j, double *__restrict__ status_est,
-                                   int32_t *__restrict__ status_flag) {
-    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sy >= st.n_sys) return;
+// The last reduction of the iteration runs in the same launch, one workgroup per system:
+// |w|^2 of system sy from the chunk partials (the same sum reduce_sys_kernel forms), then
+// the step in thread 0.
+__global__ __launch_bounds__(256) void norm_givens_kernel(GivensState st, const int32_t *__restrict__ sys_chunk_ptr,
+                                                          const double *__restrict__ partial, int ld_partial,
+                                                          double *nrm2, int j,  // aliases st.nrm2
+                                                          double *__restrict__ status_est,
+                                                          int32_t *__restrict__ status_flag) {
+    __shared__ double sh[4];
+    const int sy = blockIdx.x;
+    const double v = sys_sum(sys_chunk_ptr, partial, ld_partial, 0, sy, sh);
+    if (threadIdx.x != 0) return;
+    nrm2[sy] = v;  // st.nrm2 points here: read back by this thread in givens_column
     const int flag = givens_column(st, j, sy);
     status_est[sy] = st.est[sy];
     status_flag[sy] = flag;
@@ -298,10 +314,13 @@ int launch_givens_init(const GivensState &st, hipStream_t s) {
     return MFS_OK;
 }
 
-int launch_givens_step(const GivensState &st, int j, double *status_est, int32_t *status_flag, hipStream_t s) {
+int launch_givens_step(const GivensState &st, const int32_t *sys_chunk_ptr, const double *partial, int ld_partial,
+                       double *nrm2, int j, double *status_est, int32_t *status_flag, hipStream_t s) {
     if (st.n_sys == 0) return MFS_OK;
     if (j < 0 || j >= st.cap) return fail(MFS_EINVAL, "internal: GMRES step beyond the Krylov capacity");
-    givens_step_kernel<<<(unsigned)((st.n_sys + 63) / 64), 64, 0, s>>>(st, j, status_est, status_flag);
+    if (nrm2 != st.nrm2) return fail(MFS_EINVAL, "internal: the step's norm buffer must be the Givens state's");
+    norm_givens_kernel<<<(unsigned)st.n_sys, 256, 0, s>>>(st, sys_chunk_ptr, partial, ld_partial, nrm2, j, status_est,
+                                                          status_flag);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -1523,11 +1523,10 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
         MFS_TRY(launch_axpy_dot(nc, ck, V, n, j + 1, dots, 2 * ldh, -1.0, w, V, n, j + 1, part, ldp, s));
         MFS_TRY(launch_reduce_sys(S, scp, part, ldp, j + 1, dots + ldh, 2 * ldh, s));
         MFS_TRY(launch_axpy_dot(nc, ck, V, n, j + 1, dots + ldh, 2 * ldh, -1.0, w, w, 0, 1, part, ldp, s));
-        MFS_TRY(launch_reduce_sys(S, scp, part, ldp, 1, p->nrm.as<double>(), 1, s));
-        // the status slot written here was last read for iteration j - 3, before iteration
-        // j - 1 was enqueued
+        // |w|^2 and the Givens step in one launch; the status slot written here was last read
+        // for iteration j - 3, before iteration j - 1 was enqueued
         char *dslot = p->d_stat + (size_t)(j % mfs_plan_s::STAT_SLOTS) * sb;
-        MFS_TRY(launch_givens_step(st, j, reinterpret_cast<double *>(dslot),
+        MFS_TRY(launch_givens_step(st, scp, part, ldp, p->nrm.as<double>(), j, reinterpret_cast<double *>(dslot),
                                    reinterpret_cast<int32_t *>(dslot + 8 * (size_t)S), s));
         MFS_HIP_TRY(hipEventRecord(p->stat_ev[j % mfs_plan_s::STAT_SLOTS], s));
         MFS_TRY(launch_scale_sys(nc, p->chunks.as<VecChunk>(), w, st.scale, 1, V + (int64_t)(j + 1) * n, s));

@@ -281,7 +281,10 @@ int launch_givens_init(const GivensState &st, hipStream_t s);
 // ratio[b] = 1 / (||R||_F ||R^-1||_F).  tau: [batch][n] scratch.
 int qr_inverse_batched(int batch, double *A, int m, int n, int64_t stride_a, double *Q, int64_t stride_q, double *X,
                        int64_t stride_x, double *tau, double *ratio, hipStream_t s);
-int launch_givens_step(const GivensState &st, int j, double *status_est, int32_t *status_flag, hipStream_t s);
+// Iteration j's last reduction (|w|^2 per system from the chunk partials, into nrm2, which
+// must be st.nrm2) and its Givens step, writing the iteration's status block.
+int launch_givens_step(const GivensState &st, const int32_t *sys_chunk_ptr, const double *partial, int ld_partial,
+                       double *nrm2, int j, double *status_est, int32_t *status_flag, hipStream_t s);
 int launch_givens_solve(const GivensState &st, double *coef, int ld_coef, int nvec, hipStream_t s);
 
 }  // namespace mfs
