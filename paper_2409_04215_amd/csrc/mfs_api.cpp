@@ -1458,11 +1458,11 @@ int apply_A(mfs_plan p, MatvecFn A, const double *v, double *w, int prec, hipStr
 // iteration j + 1 while iteration j runs: it only waits for the status block of iteration
 // j - 1 (one small asynchronous copy) to count matvecs, report progress and stop once no
 // system is live.  A system that stops drops out of the matvec mask on the device, before
-// the next matvec; the one iteration enqueued after the last system stopped finds no live
-// system and does no pair work.
+// the next matvec; an iteration enqueued after the last system stopped finds no live system
+// and does no pair work.  beta holds the per-system norms of r (the caller has them already).
 int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, const std::vector<double> &target,
                   int max_iter, std::vector<int> &active, std::vector<int> &counts, std::vector<double> &est,
-                  hipStream_t s) {
+                  const std::vector<double> &beta, hipStream_t s) {
     const int S = (int)p->n_sys;
     const int64_t n = p->n_gamma;
     const int nc = (int)p->h_chunks.size();
@@ -1470,8 +1470,6 @@ int gmres_attempt(mfs_plan p, MatvecFn A, int prec, const double *r, double *x, 
     const int ldh = p->gm_cap + 2;
     double *V = p->V.as<double>();
     double *w = p->Wv.as<double>();
-    std::vector<double> beta;
-    MFS_TRY(sys_norms(p, r, beta, s));
     std::vector<int> act(S, 0);
     int n_act = 0;
     for (int sy = 0; sy < S; ++sy) {
@@ -1631,15 +1629,16 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
     int status = MFS_OK;
     if (p->prec == MFS_FP64) {
-        MFS_TRY(gmres_attempt(p, A, MFS_FP64, r, x, target, max_iter, active, counts, est, s));
+        MFS_TRY(gmres_attempt(p, A, MFS_FP64, r, x, target, max_iter, active, counts, est, bn, s));
         for (int sy = 0; sy < S; ++sy) {
             rn[sy] = est[sy];
             if (!(est[sy] <= tol * bn[sy])) status = MFS_NOT_CONVERGED;
         }
     } else {
+        std::vector<double> rnorm = bn;  // norms of r = b - A x, here with x = 0
         for (int attempt = 0; attempt <= max_refine; ++attempt) {
             if (std::find(active.begin(), active.end(), 1) == active.end()) break;
-            MFS_TRY(gmres_attempt(p, A, MFS_MIXED, r, x, target, max_iter, active, counts, est, s));
+            MFS_TRY(gmres_attempt(p, A, MFS_MIXED, r, x, target, max_iter, active, counts, est, rnorm, s));
             // true residual in FP64 (the attempt ended with a synchronisation, so the pinned
             // mask buffer is free)
             std::copy(active.begin(), active.end(), p->h_act);
@@ -1650,7 +1649,7 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
                 checks[sy] += active[sy];
             }
             MFS_TRY(launch_sub(n, b, p->Wv.as<double>(), r, s));
-            std::vector<double> tn;
+            std::vector<double> &tn = rnorm;
             MFS_TRY(sys_norms(p, r, tn, s));
             bool all = true;
             for (int sy = 0; sy < S; ++sy) {
