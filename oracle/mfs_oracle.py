@@ -50,14 +50,17 @@ _LIB = None
 
 
 def _lib():
-    """Load (building if needed) the oracle's own C pair sums."""
+    """Load (building if needed) the oracle's own C pair sums.  With
+    MFS_ORACLE_NATIVE=1 the -O3 -march=native build of the same source (for
+    the long runs that write stored reference solutions)."""
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle_p2p.so")
+        native = os.environ.get("MFS_ORACLE_NATIVE") == "1"
+        path = os.path.join(_HERE, "liboracle_p2p_native.so" if native else "liboracle_p2p.so")
         src = os.path.join(_HERE, "p2p_ref.c")
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
             from . import build_oracle
-            build_oracle.build(force=True)
+            build_oracle.build(force=True, native=native)
         lib = ctypes.CDLL(path)
         d = ctypes.POINTER(ctypes.c_double)
         i32 = ctypes.POINTER(ctypes.c_int32)
@@ -533,7 +536,15 @@ class Problem:
         dR/dc collects pair terms w_i . G(x_i - y_j) sigma_j over off-body
         pairs, sigma = (I - L) S_L^+ gamma + s_0 (the full strength: the
         self-included right-hand side only adds same-body pairs, which do
-        not move relative to each other)."""
+        not move relative to each other).
+
+        The info dict also holds dJ/d(net) ("grad_net", net layout): the given
+        net quantities enter only through the completion strengths s_0 in
+        b = -sum_{k'} S^(kk') s_0^(k'), self block included (eqs. (erhsK),
+        (stou0)), so dJ/ds_0^(k') = -sum_k S^(kk')T w^(k), and with
+        s_0 = (q/N) 1 (eq. (al0)) or K_N (K_N^T K_N)^{-1} [f; t] (eqs.
+        (lambda01), (lambda02)) the chain rule gives dJ/dq = mean of that, or
+        dJ/d[f; t] = (K_N^T K_N)^{-1} K_N^T of it."""
         sol = self.solve(net, tol=tol, max_iter=max_iter)
         U = np.asarray(sol["out"])
         if self.kind == STOKES:
@@ -548,7 +559,19 @@ class Problem:
         grad = np.zeros((len(self.bodies), 3))
         np.add.at(grad, self.trg_body, gx)
         np.add.at(grad, self.src_body, gy)
-        return float(np.sum(U * U)), -grad, dict(sol=sol, w=w, adj_iters=it_adj)
+        # S^(kk')T w at the proxies of k' from the collocation points of every k
+        # (same-body pairs included: the right-hand side sums all of them)
+        t = -p2p(self.kind, self.Y, self.src_body, self.X, self.trg_body, w.reshape(shape), self.mu,
+                 False).reshape(-1)
+        gnet = []
+        for k, b in enumerate(self.bodies):
+            tk = self.sblock(t, k)
+            if self.kind == LAPLACE:
+                gnet.append(np.mean(tk))
+            else:
+                KN = K_matrix(b.Y, b.centre)
+                gnet.append(np.linalg.solve(KN.T @ KN, KN.T @ tk))
+        return float(np.sum(U * U)), -grad, dict(sol=sol, w=w, adj_iters=it_adj, grad_net=np.array(gnet))
 
 
 # ---------------------------------------------------------------------------

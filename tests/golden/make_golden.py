@@ -1,9 +1,14 @@
-"""Writes the oracle's solutions of the 100-ellipsoid workload (FP64, GMRES
-tol 1e-10) to text files next to this script.  Calls only oracle/ and the
-seeded input generators; takes a few minutes on 8 cores.
+"""Writes stored oracle results (FP64, GMRES tol 1e-10) to text files next to
+this script.  Calls only oracle/ and the seeded input generators.
 
-    python tests/golden/make_golden.py            # mobility / elastance solutions
-    python tests/golden/make_golden.py two_way    # resistance -> mobility (2-way error)
+    python tests/golden/make_golden.py            # ellipsoids_100 mobility / elastance (minutes)
+    python tests/golden/make_golden.py two_way    # ellipsoids_100 resistance -> mobility (2-way error)
+    python tests/golden/make_golden.py rows_10000 # 10^4 Type T case: 1000 sampled rows (tens of minutes)
+    python tests/golden/make_golden.py batched    # batched_64: a stated subset of the 64 systems (~1.5 h)
+    python tests/golden/make_golden.py e1000_laplace | e1000_stokes   # ellipsoids_1000 (~1 h / ~4 h)
+
+The long runs set MFS_ORACLE_NATIVE=1 (the oracle's C loops built with
+-O3 -march=native; same source) to fit in hours on 8 cores.
 """
 import os
 import sys
@@ -18,6 +23,38 @@ sys.path.insert(0, ROOT)
 import mfs_workloads as W  # noqa: E402
 from oracle import mfs_oracle as O  # noqa: E402
 
+TOL = 1e-10
+# batched_64: the systems stored are every system of at most this many bodies
+# plus the largest system of each kind.
+BATCHED_SMALL = 150
+
+
+def _log(*a):
+    print(time.strftime("%H:%M:%S"), *a, flush=True)
+
+
+def _logged(pr, what):
+    """The oracle's matvec with one log line per call (progress of hour-long solves)."""
+    count = [0]
+    t0 = time.time()
+
+    def mv(g):
+        count[0] += 1
+        out = pr.matvec(g)
+        _log(f"{what}: matvec {count[0]} done, {time.time() - t0:.0f} s")
+        return out
+    return mv
+
+
+def _solve(pr, net, what):
+    """Problem.solve with a progress line per matvec (same steps: rhs, GMRES, extract)."""
+    t0 = time.time()
+    b, s0 = pr.rhs(net)
+    _log(f"{what}: right-hand side done, {time.time() - t0:.0f} s")
+    gamma, iters, hist = O.gmres(_logged(pr, what), b, TOL)
+    out, lam, sigma = pr.extract(gamma, s0)
+    return dict(out=out, iters=iters, hist=hist, secs=time.time() - t0)
+
 
 def two_way():
     """Resistance solve of ellipsoids_100 (proxies at the resistance scale) with
@@ -27,7 +64,7 @@ def two_way():
     wr = W.with_proxy_scale(wl, W.resistance_proxy_scale())
     U_ref = np.random.default_rng(np.random.SeedSequence(7100)).standard_normal((wl.n_body, 6))
     t0 = time.time()
-    r = O.two_way_error(O.ResistanceProblem.from_workload(wr), O.Problem.from_workload(wl), U_ref, tol=1e-10)
+    r = O.two_way_error(O.ResistanceProblem.from_workload(wr), O.Problem.from_workload(wl), U_ref, tol=TOL)
     dt = time.time() - t0
     hdr = (f"2-way test of the seeded ellipsoids_100 workload: columns U_ref (6), F (6), U (6) per body;\n"
            f"resistance proxies at scale {W.resistance_proxy_scale():.6f}, mobility at 0.7; U_ref from "
@@ -39,14 +76,12 @@ def two_way():
     print("two_way", r["iters_res"], r["iters_mob"], r["eps"], f"{dt:.0f}s", flush=True)
 
 
-def main():
-    if len(sys.argv) > 1 and sys.argv[1] == "two_way":
-        return two_way()
+def e100():
     for kind, name, what in ((W.STOKES, "ellipsoids_100_stokes_U.txt", "rigid velocities [v; omega] per body"),
                              (W.LAPLACE, "ellipsoids_100_laplace_phi.txt", "potentials per body")):
         wl = W.ellipsoids_100(kind)
         t0 = time.time()
-        sol = O.Problem.from_workload(wl).solve(wl.net[0], tol=1e-10)
+        sol = O.Problem.from_workload(wl).solve(wl.net[0], tol=TOL)
         dt = time.time() - t0
         out = np.asarray(sol["out"]).reshape(wl.n_body, -1)
         hdr = (f"oracle solution of the seeded ellipsoids_100 workload ({'Stokes mobility' if kind else 'Laplace elastance'}),\n"
@@ -54,6 +89,99 @@ def main():
                f"Written by tests/golden/make_golden.py (oracle only).")
         np.savetxt(os.path.join(HERE, name), out, fmt="%.17e", header=hdr)
         print(name, sol["iters"], f"{dt:.0f}s", flush=True)
+
+
+def e1000(kind):
+    """Oracle solution of ellipsoids_1000 (Section 3.3 recovery, eqs. (vkal), (getU))."""
+    name = "ellipsoids_1000_stokes_U.txt" if kind == W.STOKES else "ellipsoids_1000_laplace_phi.txt"
+    wl = W.ellipsoids_1000(kind)
+    pr = O.Problem.from_workload(wl)
+    sol = _solve(pr, wl.net[0], f"ellipsoids_1000 kind {kind}")
+    out = np.asarray(sol["out"]).reshape(wl.n_body, -1)
+    hdr = (f"oracle solution of the seeded ellipsoids_1000 workload "
+           f"({'Stokes mobility, [v; omega]' if kind else 'Laplace elastance, phi'} per body);\n"
+           f"FP64 oracle (C loops built -O3 -march=native), GMRES tol {TOL:g}, {sol['iters']} iterations, "
+           f"{sol['secs']:.0f} s on {O.oracle_threads()} threads; final residual estimate {sol['hist'][-1]:.3e}.\n"
+           f"Written by tests/golden/make_golden.py (oracle only).")
+    np.savetxt(os.path.join(HERE, name), out, fmt="%.17e", header=hdr)
+    _log(name, sol["iters"], f"{sol['secs']:.0f}s")
+
+
+def batched_subset(wl):
+    """The stored subset of batched_64: every system of at most BATCHED_SMALL
+    bodies, and the largest system of each kind."""
+    sizes = np.diff(wl.sys_body_ptr)
+    pick = [s for s in range(wl.n_sys) if sizes[s] <= BATCHED_SMALL]
+    for kind in (W.LAPLACE, W.STOKES):
+        idx = [s for s in range(wl.n_sys) if wl.sys_kind[s] == kind]
+        pick.append(max(idx, key=lambda s: sizes[s]))
+    return sorted(set(pick), key=lambda s: (sizes[s], s))
+
+
+def batched():
+    """Oracle solutions of a subset of batched_64's suspensions, each solved on
+    its own (the systems are independent).  Rows: system, body, then phi
+    (Laplace, one column, padded with zeros) or [v; omega] (Stokes, six)."""
+    wl = W.batched_64()
+    sizes = np.diff(wl.sys_body_ptr)
+    rows, notes = [], []
+    path = os.path.join(HERE, "batched_64_subset.txt")
+    t_all = time.time()
+    for s in batched_subset(wl):
+        pr = O.Problem.from_workload(wl, s)
+        sol = _solve(pr, wl.net[s], f"batched_64 system {s} ({sizes[s]} bodies, kind {wl.sys_kind[s]})")
+        out = np.asarray(sol["out"]).reshape(sizes[s], -1)
+        pad = np.zeros((sizes[s], 6))
+        pad[:, :out.shape[1]] = out
+        rows.append(np.concatenate([np.full((sizes[s], 1), s), np.arange(sizes[s])[:, None], pad], axis=1))
+        notes.append(f"{s}:{sol['iters']}")
+        hdr = (f"oracle solutions of a subset of the seeded batched_64 workload: every system of at most "
+               f"{BATCHED_SMALL} bodies and the largest of each kind.\n"
+               f"Columns: system, body (within the system), then phi (Laplace; other columns 0) or [v; omega] (Stokes).\n"
+               f"FP64 oracle (C loops built -O3 -march=native), each system solved alone, GMRES tol {TOL:g}; "
+               f"system:iterations {' '.join(notes)}; {time.time() - t_all:.0f} s.\n"
+               f"Written by tests/golden/make_golden.py batched (oracle only).")
+        np.savetxt(path, np.concatenate(rows), fmt="%.17e", header=hdr)
+        _log(f"system {s} stored, {sol['iters']} iterations")
+
+
+def rows_10000():
+    """The paper's 10^4 Type T case (Section 4.2): right-hand side and the matvec
+    of a seeded random vector and of a seeded smooth field, on 1000 sampled
+    collocation rows, each computed by the oracle over all sources."""
+    t0 = time.time()
+    wl = W.ellipsoids_10000(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    _log(f"10^4: workload and oracle set-up, {time.time() - t0:.0f} s")
+    rows = np.sort(np.random.default_rng(86).choice(pr.X.shape[0], 1000, replace=False))
+    g = W.random_vector(pr.n_gamma, 87)
+    sm = W.smooth_vector(wl, 88)
+    ref_b, _ = pr.rhs(wl.net[0], rows=rows)
+    _log(f"10^4: right-hand side rows, {time.time() - t0:.0f} s")
+    ref_g = pr.matvec(g, rows=rows)
+    _log(f"10^4: matvec rows (random), {time.time() - t0:.0f} s")
+    ref_sm = pr.matvec(sm, rows=rows)
+    _log(f"10^4: matvec rows (smooth), {time.time() - t0:.0f} s")
+    tab = np.concatenate([rows[:, None].astype(np.float64), ref_b.reshape(-1, 3), ref_g.reshape(-1, 3),
+                          ref_sm.reshape(-1, 3)], axis=1)
+    hdr = ("the seeded ellipsoids_10000 workload (10^4 Type T ellipsoids, N = 658, M = 842, Stokes):\n"
+           "1000 collocation rows drawn by default_rng(86); columns: row, right-hand side b (3), "
+           "A g (3) for g = random_vector(n_gamma, 87), A s (3) for s = smooth_vector(88).\n"
+           f"FP64 oracle over all 6.58e6 proxies per row, {time.time() - t0:.0f} s.  "
+           "Written by tests/golden/make_golden.py rows_10000 (oracle only).")
+    np.savetxt(os.path.join(HERE, "ellipsoids_10000_rows.txt"), tab, fmt="%.17e", header=hdr)
+    _log("10^4 rows stored")
+
+
+JOBS = {"two_way": two_way, "rows_10000": rows_10000, "batched": batched,
+        "e1000_laplace": lambda: e1000(W.LAPLACE), "e1000_stokes": lambda: e1000(W.STOKES)}
+
+
+def main():
+    if len(sys.argv) == 1:
+        return e100()
+    for job in sys.argv[1:]:
+        JOBS[job]()
 
 
 if __name__ == "__main__":

@@ -17,7 +17,8 @@ independently of the oracle's own formulas (CPU only).
   constant potential / rigid motion at the collocation nodes of one body.
 * Symmetry and positivity of the mobility matrix, translation invariance,
   rotation covariance, two-body far-field asymptotics.
-* Adjoint: dot-product identity and central finite differences of the loss.
+* Adjoint: dot-product identity and central finite differences of the loss,
+  with respect to the centres and to the given net quantities.
 * Capacitance / resistance (Section 2, Algorithm 1): one sphere's drag, torque
   and capacitance; P = 1 least squares with the net quantities of eqs.
   (qkgauss), (force_eq); the matvec of eq. (2sysprec) assembled from dense
@@ -319,6 +320,45 @@ def test_velocity_loss_gradient_matches_finite_differences(kind):
         Jm = np.sum(O.Problem(kind, wl.shapes, cm, wl.rot, wl.shape_of_body).solve(F, tol=1e-13)["out"] ** 2)
         fd = (Jp - Jm) / (2 * h)
         assert abs(fd - grad[k, a]) < 1e-6 * np.abs(grad).max(), (k, a, fd, grad[k, a])
+
+
+def _net_gradient_vs_fd(kind):
+    wl = W.small_cluster(3, kind, 30, 60, seed=21)
+    F = np.asarray(wl.net[0], np.float64)
+    pr = O.Problem.from_workload(wl)
+    _, _, info = pr.velocity_loss_gradient(F, tol=1e-13)
+    g = info["grad_net"].reshape(F.shape)
+    h = 1e-3
+    worst = 0.0
+    for idx in np.ndindex(*F.shape):
+        Fp, Fm = F.copy(), F.copy()
+        Fp[idx] += h
+        Fm[idx] -= h
+        Jp = np.sum(pr.solve(Fp, tol=1e-13)["out"] ** 2)
+        Jm = np.sum(pr.solve(Fm, tol=1e-13)["out"] ** 2)
+        worst = max(worst, abs((Jp - Jm) / (2 * h) - g[idx]))
+    return worst / np.abs(g).max()
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_net_quantity_gradient_matches_finite_differences(kind, monkeypatch):
+    """dJ/dF (forces and torques) or dJ/dq (charges) of J = sum |U|^2 or
+    sum phi^2 against central differences of whole solves with one given net
+    component moved.  J is quadratic in the net quantities (U is linear in
+    them), so the central difference is exact up to the solver's rounding.
+    Planted mistake: the transposed sum of the gradient leaves out the
+    same-body pairs that the right-hand side includes; the pin must fail."""
+    assert _net_gradient_vs_fd(kind) < 1e-9
+    good_p2p = O.p2p
+
+    def p2p_adjoint_without_self(k, X, tb, Y, sb, st, mu=1.0, skip_same_body=True):
+        # only the transposed call has 30 targets per body (proxies as targets)
+        if not skip_same_body and np.asarray(X).shape[0] == 3 * 30:
+            skip_same_body = True
+        return good_p2p(k, X, tb, Y, sb, st, mu, skip_same_body)
+
+    monkeypatch.setattr(O, "p2p", p2p_adjoint_without_self)
+    assert _net_gradient_vs_fd(kind) > 1e-3
 
 
 # ---------------------------------------------------------------------------
