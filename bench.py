@@ -372,7 +372,7 @@ def main():
         pairs_mx = sum(m * off for (k, off, rhs), m in zip(per_sys, mx))
         its = info["iters"]
         if grad:
-            g, _, _, _ = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=args.tol)
+            g, _, _, _, _ = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=args.tol)
             amx, af64 = plan.last_solve()
             # adjoint matvecs (transposed pair sums) + the two position-gradient passes
             pairs += sum((m + f + 2) * off for (k, off, rhs), m, f in zip(per_sys, amx, af64))

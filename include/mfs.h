@@ -12,7 +12,8 @@
  * its pieces (all-pairs fundamental-solution sums, per-body pseudo-inverse
  * blocks, rigid-body / constant projection), the right-hand side, GMRES
  * around it, the recovery of potentials or rigid velocities, and the adjoint
- * of all of these for gradients with respect to particle centres.
+ * of all of these for gradients with respect to particle centres and to the
+ * given net quantities.
  *
  * Conventions that hold for every entry point
  * ------------------------------------------
@@ -292,18 +293,34 @@ int mfs_extract(mfs_plan plan, const double *gamma, const double *strength0, dou
  * out = q^(k) = sum_j alpha_j (eq. (qkgauss)) or [f; t] = K_N^T lambda
  * (eq. (force_def)); sigma receives lambda. */
 
-/* Gradient of a loss J(out) with respect to the body centres, through the
- * whole solve (bodies move rigidly with their centres; shapes, rotations and
- * net quantities are held fixed).  Inputs: the forward solution gamma and
- * strength0 (from mfs_rhs), grad_out = dJ/d(out) [device, net layout].
- * Output: grad_centre [device][n_body][3].  One adjoint GMRES (A^T w = g with
- * g = (S_L^+)^T dJ/dlambda), then the backward pair sums over off-body
- * pairs.  iters/relres as for mfs_gmres_solve (adjoint solve).  Derived from
- * the square system; the paper has no gradients.  Synchronous. */
-int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strength0, const double *grad_out,
-                       double *grad_centre, double tol, int32_t max_iter, int32_t max_refine,
-                       int32_t *iters, double *relres, void *stream);
-/* (MFS_MOBILITY plans only; MFS_EUNSUPPORTED for MFS_RESISTANCE.) */
+/* Gradients of a loss J(out) through the whole solve, with respect to the
+ * body centres and to the given net quantities (charges q, or forces and
+ * torques [f; t]).  Bodies move rigidly with their centres; shapes and
+ * rotations are held fixed.  Derived from the square system of eq.
+ * (2esysprec); the paper has no gradients.
+ * Inputs [device]: the forward solution gamma (gamma layout) and strength0
+ * (lambda layout, from mfs_rhs), grad_out = dJ/d(out) (net layout).
+ * Outputs [device], either may be NULL but not both:
+ *   grad_centre [n_body][3]  dJ/dc.  Requires strength0: the pair terms carry
+ *                            the full strength (I - L) S_L^+ gamma + s_0.
+ *   grad_net    (net layout) dJ/dq or dJ/d[f; t].  The net quantities enter
+ *                            only through s_0 (eqs. (al0), (lambda01),
+ *                            (lambda02)) in b = -u_0 (eqs. (erhsK), (stou0)):
+ *                            grad_net = (1/N) 1^T t (Laplace) or
+ *                            (K_N^T K_N)^{-1} K_N^T t (Stokes) with
+ *                            t = -sum_k S^(kk')T w^(k), self block included.
+ * Work: one adjoint GMRES, A^T w = g with g = (S_L^+)^T dJ/dlambda (the
+ * plan's precision; tol, max_iter, max_refine, iters and relres as for
+ * mfs_gmres_solve with adjoint = 1), then the backward pair sums over
+ * off-body pairs (grad_centre) and one transposed pair sum over all pairs
+ * (grad_net).  MFS_EINVAL for a NULL plan, gamma or grad_out, for neither
+ * output, for grad_centre without strength0, or for bad tol / max_iter /
+ * max_refine; MFS_EUNSUPPORTED in a MFS_RESISTANCE plan.  Returns
+ * MFS_NOT_CONVERGED (outputs from the best adjoint iterate) when the adjoint
+ * solve ends above tol.  Synchronous. */
+int mfs_gmres_solve_backward(mfs_plan plan, const double *gamma, const double *strength0, const double *grad_out,
+                             double *grad_centre, double *grad_net, double tol, int32_t max_iter,
+                             int32_t max_refine, int32_t *iters, double *relres, void *stream);
 
 /* Surface residual at test points on every body surface, with u the
  * representation of the full strengths sigma [device, lambda layout, e.g. from
@@ -312,7 +329,7 @@ int mfs_solve_backward(mfs_plan plan, const double *gamma, const double *strengt
  * resistance solve].  Stokes (eq. (residual)): eps(x) = |u(x) - g(x)| / |g(x)|
  * with g = v + omega x (x - c), the body's rigid motion.  Laplace: the
  * absolute error eps(x) = |u(x) - phi| against the body's potential phi, the
- * measure of the elastance convergence study (Sec. 6, Fig. f:elastconv(a)).  Test points per shape in the shape frame:
+ * measure of the elastance convergence study (Sec. 4.1, Fig. f:elastconv(a)).  Test points per shape in the shape frame:
  * shape_n_test [host][n_shape], shape_test [host] concatenated, sum x 3.
  * eps [device] body by body; u_test [device, optional] receives u at the
  * points (3 or 1 values per point).  prec selects the pair arithmetic.
@@ -347,7 +364,7 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
 /* Progress of long solves.  With a callback set, mfs_gmres_solve (and the
- * adjoint solve of mfs_solve_backward) calls it on the calling host thread
+ * adjoint solve of mfs_gmres_solve_backward) calls it on the calling host thread
  * after every GMRES iteration with: the matvecs spent so far (largest over
  * systems), the number of systems still iterating, and the largest relative
  * residual estimate among the systems of the current attempt.  A non-zero

@@ -334,7 +334,7 @@ def smooth_vector(wl: Workload, seed: int) -> np.ndarray:
 
 def elastance_spheres(n_src: int = 969, n_trg: int = 1123, n_body: int = 10, delta: float = 0.1,
                       seed: int = 0) -> Workload:
-    """The paper's small elastance test (Section 6): n_body unit spheres grown
+    """The paper's small elastance test (Section 4.1): n_body unit spheres grown
     compactly from the origin at minimum gap delta (compact_sphere_cluster),
     N proxies on the concentric sphere of radius R_p = 0.7 and M collocation
     points on the surface (N = 969, M = 1123 as in the paper), Fibonacci point

@@ -272,7 +272,7 @@ def grown_sphere_cluster(rng: np.random.Generator, n: int, delta: float, radius:
 
 def compact_sphere_cluster(rng: np.random.Generator, n: int, delta: float, radius: float = 1.0) -> np.ndarray:
     """Centres of n spheres grown from the origin as in the paper's small
-    elastance test (Section 6): the first sphere sits at the origin; each new one
+    elastance test (Section 4.1): the first sphere sits at the origin; each new one
     is placed along a uniformly random direction u at the smallest distance t
     from the origin where its surface gap to every placed sphere is at least
     delta, so the gap to at least one of them is exactly delta.  For a placed

@@ -487,7 +487,7 @@ class Problem:
         included).  Stokes: eps_res(x) = |u(x) - g(x)| / |g(x)| with g the
         body's rigid motion v + omega x (x - c) (eq. (residual)).  Laplace: the
         absolute error |u(x) - phi_k| against the body's potential, the
-        quantity whose maximum the elastance convergence study plots (Sec. 6,
+        quantity whose maximum the elastance convergence study plots (Sec. 4.1,
         Fig. f:elastconv(a)).
         test_local: (n_t, 3) points on the surface of the shape, body frame
         (one shape for all bodies).  Returns eps stacked body by body."""

@@ -5,9 +5,11 @@
 //    factor are one GEMM: the columns are the bodies' vectors rotated into the
 //    shape frame (Remark "congruent": lambda = R V Sigma^+ U^T R^T gamma).
 //    GEMMs run on the matrix cores: v_mfma_f32_32x32x2_f32 (mixed) or
-//    v_mfma_f64_16x16x4_f64 (FP64), one 32x32 output tile per wave loaded
-//    straight into registers, one launch for every (factor, body-column)
-//    tile of every shape.
+//    v_mfma_f64_16x16x4_f64 (FP64).  One workgroup per 32x32 output tile;
+//    its four waves split the tile's K range, each streaming its A rows and
+//    B columns through a wave-private LDS stage with coalesced loads, and
+//    their partial tiles are added through LDS.  One launch covers every
+//    (factor, body-column) tile of every shape.
 //  * Projection (I - L): constants for Laplace (Section 3.1); rigid motions
 //    L = K_N (K_N^T K_N)^{-1} K_N^T for Stokes (Section 3.2).  Never formed:
 //    a 6-vector reduction w = K_N^T v, z = G^{-1} w, v - K_N z.  FP64.
@@ -563,6 +565,44 @@ __global__ void grad_lambda_kernel(BodyView bv, const double *__restrict__ gout,
     }
 }
 
+// dJ/d(net) from t = dJ/ds_0 (lambda layout; the completion strengths enter b
+// = -S s_0 with the self block): Laplace s_0 = (q/N) 1 gives dJ/dq = mean(t);
+// Stokes s_0 = K_N G^{-1} [f; t] gives dJ/d[f; t] = G^{-1} K_N^T t (G symmetric).
+__global__ __launch_bounds__(256) void grad_net_kernel(BodyView bv, const double *__restrict__ t,
+                                                       double *__restrict__ gnet) {
+    __shared__ double sh[4][6];
+    const int64_t b = blockIdx.x;
+    const int kind = bv.kind[b];
+    const int n = bv.n_src[b];
+    const int64_t off = bv.lam_off[b];
+    const int64_t row0 = bv.src_row[b];
+    if (kind == MFS_LAPLACE) {
+        double s[1] = {0.0};
+        for (int j = threadIdx.x; j < n; j += blockDim.x) s[0] += t[off + j];
+        block_sum<1>(s, reinterpret_cast<double(*)[1]>(sh));
+        if (threadIdx.x == 0) gnet[bv.net_off[b]] = s[0] / n;
+        return;
+    }
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double *v = t + off + 3 * j;
+        const double *d = bv.src_off64 + 4 * (row0 + j);
+        double c[3];
+        cross3(d, v, c);
+        w[0] += v[0]; w[1] += v[1]; w[2] += v[2];
+        w[3] += c[0]; w[4] += c[1]; w[5] += c[2];
+    }
+    block_sum<6>(w, sh);
+    if (threadIdx.x == 0) {
+        const double *Gi = bv.gram_inv + 36 * b;
+        for (int r = 0; r < 6; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < 6; ++c) acc += Gi[6 * r + c] * w[c];
+            gnet[bv.net_off[b] + r] = acc;
+        }
+    }
+}
+
 __global__ void set_src_strength_kernel(BodyView bv, const double *__restrict__ str, void *__restrict__ srcS,
                                         void *__restrict__ srcL, int prec) {
     const int64_t b = blockIdx.x;
@@ -810,6 +850,13 @@ int launch_dirichlet_rhs(const BodyView &bv, const double *data, double *b, hipS
 int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s) {
     if (bv.n_body == 0) return MFS_OK;
     grad_lambda_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, grad_out, glam);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
+int launch_grad_net(const BodyView &bv, const double *t, double *gnet, hipStream_t s) {
+    if (bv.n_body == 0) return MFS_OK;
+    grad_net_kernel<<<(unsigned)bv.n_body, 256, 0, s>>>(bv, t, gnet);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

@@ -153,7 +153,7 @@ __global__ void field_reduce_kernel(int64_t n, const double *__restrict__ partia
 
 // Surface residual per test point.  Stokes: eps(x) = |u(x) - g(x)| / |g(x)| with g = v + omega x (x - c)
 // from the body's rigid motion (eq. (residual)).  Laplace: the absolute error |u(x) - phi_k| against the
-// body potential, the measure of the elastance convergence study (Sec. 6, Fig. f:elastconv(a)); a relative
+// body potential, the measure of the elastance convergence study (Sec. 4.1, Fig. f:elastconv(a)); a relative
 // one would divide by potentials that may be near zero.
 __global__ void residual_kernel(int64_t n, const int32_t *__restrict__ body, const int32_t *__restrict__ kind,
                                 const int64_t *__restrict__ net_off, const double *__restrict__ off64,

@@ -1706,13 +1706,17 @@ extern "C" int mfs_plan_set_progress(mfs_plan p, mfs_progress_fn fn, void *user)
     return MFS_OK;
 }
 
-extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double *strength0, const double *grad_out,
-                                  double *grad_centre, double tol, int32_t max_iter, int32_t max_refine, int32_t *iters,
-                                  double *relres, void *stream) {
+extern "C" int mfs_gmres_solve_backward(mfs_plan p, const double *gamma, const double *strength0,
+                                        const double *grad_out, double *grad_centre, double *grad_net, double tol,
+                                        int32_t max_iter, int32_t max_refine, int32_t *iters, double *relres,
+                                        void *stream) {
     if (!p) return fail(MFS_EINVAL, "NULL plan");
     if (p->formulation != MFS_MOBILITY)
-        return fail(MFS_EUNSUPPORTED, "centre gradients are defined for the mobility / elastance formulation");
-    if (!gamma || !grad_out || !grad_centre) return fail(MFS_EINVAL, "NULL gamma, grad_out or grad_centre");
+        return fail(MFS_EUNSUPPORTED, "gradients are defined for the mobility / elastance formulation");
+    if (!gamma || !grad_out) return fail(MFS_EINVAL, "NULL gamma or grad_out");
+    if (!grad_centre && !grad_net) return fail(MFS_EINVAL, "neither grad_centre nor grad_net requested");
+    if (grad_centre && !strength0)
+        return fail(MFS_EINVAL, "strength0 is required for grad_centre (the pair terms carry (I - L) lambda + s_0)");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFS_EINVAL, "tol must be finite and > 0");
     if (max_iter < 1 || max_iter > 2000) return fail(MFS_EINVAL, "max_iter must be in [1, 2000]");
     if (max_refine < 0 || max_refine > 100) return fail(MFS_EINVAL, "max_refine must be in [0, 100]");
@@ -1726,8 +1730,10 @@ extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double 
     MFS_TRY(p->bw_gs.reserve(std::max<int64_t>(1, 3 * p->n_srcp) * sizeof(double)));
     BodyView bv = p->view();
     // sigma = (I - L) S_L^+ gamma + s0 (FP64)
-    MFS_TRY(precond_fwd(p, gamma, MFS_FP64, false, p->ws_l64c.as<double>(), -1, s));
-    MFS_TRY(launch_extract(bv, p->ws_l64c.as<double>(), strength0, nullptr, p->bw_sigma.as<double>(), s));
+    if (grad_centre) {
+        MFS_TRY(precond_fwd(p, gamma, MFS_FP64, false, p->ws_l64c.as<double>(), -1, s));
+        MFS_TRY(launch_extract(bv, p->ws_l64c.as<double>(), strength0, nullptr, p->bw_sigma.as<double>(), s));
+    }
     // g = (S_L^+)^T dJ/dlambda
     MFS_TRY(launch_grad_lambda(bv, grad_out, p->bw_glam.as<double>(), s));
     MFS_TRY(precond_tr(p, p->bw_glam.as<double>(), MFS_FP64, false, p->bw_g.as<double>(), s));
@@ -1735,24 +1741,36 @@ extern "C" int mfs_solve_backward(mfs_plan p, const double *gamma, const double 
     int st = gmres_solve_impl(p, p->bw_g.as<double>(), p->bw_w.as<double>(), tol, max_iter, max_refine, true, iters,
                               relres, s);
     if (st < 0) return st;
-    // d(w^T R)/dx_i over off-body pairs (lanes: collocation points with w; sources: proxies with sigma)
-    MFS_TRY(set_fwd_strength(p, p->bw_sigma.as<double>(), prec, s));
-    P2PLaunch Lf = fwd_launch(p, prec);
-    Lf.skip_same = true;
-    Lf.alpha = -1.0;
-    Lf.out = p->bw_gt.as<double>();
-    Lf.n_val = 3 * p->n_trgp;
-    MFS_TRY(launch_p2p_grad(p->p2p_fwd1, Lf, p->bw_w.as<double>(), p->n_trgp, s));
-    // d(w^T R)/dy_j (lanes: proxies with sigma; sources: collocation points with w)
     MFS_TRY(set_tr_strength(p, p->bw_w.as<double>(), prec, s));
-    P2PLaunch Lt = tr_launch(p, prec);
-    Lt.skip_same = true;
-    Lt.alpha = -1.0;
-    Lt.out = p->bw_gs.as<double>();
-    Lt.n_val = 3 * p->n_srcp;
-    MFS_TRY(launch_p2p_grad(p->p2p_tr1, Lt, p->bw_sigma.as<double>(), p->n_srcp, s));
-    MFS_TRY(launch_body_grad_reduce(p->n_body, p->d_trg_row32.as<int32_t>(), p->d_src_row32.as<int32_t>(),
-                                    p->bw_gt.as<double>(), p->bw_gs.as<double>(), grad_centre, s));
+    if (grad_centre) {
+        // d(w^T R)/dx_i over off-body pairs (lanes: collocation points with w; sources: proxies with sigma)
+        MFS_TRY(set_fwd_strength(p, p->bw_sigma.as<double>(), prec, s));
+        P2PLaunch Lf = fwd_launch(p, prec);
+        Lf.skip_same = true;
+        Lf.alpha = -1.0;
+        Lf.out = p->bw_gt.as<double>();
+        Lf.n_val = 3 * p->n_trgp;
+        MFS_TRY(launch_p2p_grad(p->p2p_fwd1, Lf, p->bw_w.as<double>(), p->n_trgp, s));
+        // d(w^T R)/dy_j (lanes: proxies with sigma; sources: collocation points with w)
+        P2PLaunch Lt = tr_launch(p, prec);
+        Lt.skip_same = true;
+        Lt.alpha = -1.0;
+        Lt.out = p->bw_gs.as<double>();
+        Lt.n_val = 3 * p->n_srcp;
+        MFS_TRY(launch_p2p_grad(p->p2p_tr1, Lt, p->bw_sigma.as<double>(), p->n_srcp, s));
+        MFS_TRY(launch_body_grad_reduce(p->n_body, p->d_trg_row32.as<int32_t>(), p->d_src_row32.as<int32_t>(),
+                                        p->bw_gt.as<double>(), p->bw_gs.as<double>(), grad_centre, s));
+    }
+    if (grad_net) {
+        // dJ/ds_0 = -sum_k S^(kk')T w^(k) over every pair of the system, self block
+        // included (b = -u_0 sums them all), then the chain rule through s_0(net)
+        P2PLaunch Ln = tr_launch(p, prec);
+        Ln.skip_same = false;
+        Ln.alpha = -1.0;
+        Ln.out = p->ws_l64c.as<double>();
+        MFS_TRY(launch_p2p(p->p2p_tr, Ln, s));
+        MFS_TRY(launch_grad_net(bv, p->ws_l64c.as<double>(), grad_net, s));
+    }
     MFS_HIP_TRY(hipStreamSynchronize(s));
     return st;
 }

@@ -217,6 +217,7 @@ int launch_extract(const BodyView &bv, const double *lam, const double *s0, doub
 // Dirichlet data at the collocation points: phi 1_M or v + omega x (x - c) (gamma layout)
 int launch_dirichlet_rhs(const BodyView &bv, const double *data, double *b, hipStream_t s);
 int launch_grad_lambda(const BodyView &bv, const double *grad_out, double *glam, hipStream_t s);
+int launch_grad_net(const BodyView &bv, const double *t, double *gnet, hipStream_t s);
 int launch_set_src_strength(const BodyView &bv, const double *str, void *srcS, void *srcL, int prec, hipStream_t s);
 int launch_body_grad_reduce(int64_t n_body, const int32_t *trg_ptr, const int32_t *src_ptr, const double *gt,
                             const double *gs, double *grad_c, hipStream_t s);

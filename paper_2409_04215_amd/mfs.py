@@ -90,8 +90,8 @@ def lib():
         L.mfs_p2p_laplace_gradient.argtypes = geo + [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_surface_residual.argtypes = [_vp, _vp, _vp, _i32p, _dp, _vp, _vp, ctypes.c_int, _vp]
         L.mfs_plan_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _dp, _vp]
-        L.mfs_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
-                                         ctypes.c_int32, _i32p, _dp, _vp]
+        L.mfs_gmres_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                               ctypes.c_int32, _i32p, _dp, _vp]
         _lib = L
     return _lib
 
@@ -429,36 +429,48 @@ class Plan:
                "mfs_plan_autotune")
         return tpl.value, mi.value, ms.value
 
-    def solve_backward(self, gamma, s0, grad_out, tol=1e-5, max_iter=200, max_refine=3, stream=None):
+    def gmres_solve_backward(self, gamma, s0, grad_out, tol=1e-5, max_iter=200, max_refine=3, want_centre=True,
+                             want_net=False, stream=None, raise_not_converged: bool = False):
+        """dJ/dcentres and/or dJ/d(net) for dJ/d(out) = grad_out (mfs_gmres_solve_backward).
+        Returns (grad_centre or None, grad_net or None, iters, relres, status)."""
         n_sys = len(self.sys_kind)
-        g = torch.empty(self.centre.shape[0], 3, dtype=torch.float64, device=self.device)
+        gc = torch.empty(self.centre.shape[0], 3, dtype=torch.float64, device=self.device) if want_centre else None
+        gn = self._new(self.n_net) if want_net else None
         iters = np.zeros(n_sys, np.int32)
         relres = np.zeros(n_sys, np.float64)
-        st = lib().mfs_solve_backward(self._h, _ptr(gamma), _ptr(s0), _ptr(grad_out), _ptr(g), float(tol),
-                                      int(max_iter), int(max_refine), iters.ctypes.data_as(_i32p),
-                                      relres.ctypes.data_as(_dp), _stream(stream))
-        _check(st, "mfs_solve_backward")
-        return g, iters, relres, st
+        st = lib().mfs_gmres_solve_backward(self._h, _ptr(gamma), _ptr(s0), _ptr(grad_out), _ptr(gc), _ptr(gn),
+                                            float(tol), int(max_iter), int(max_refine), iters.ctypes.data_as(_i32p),
+                                            relres.ctypes.data_as(_dp), _stream(stream))
+        _check(st, "mfs_gmres_solve_backward", allow_warning=not raise_not_converged)
+        return gc, gn, iters, relres, st
 
 
 class MobilitySolve(torch.autograd.Function):
-    """out = solve(centres) for fixed shapes, rotations and net quantities;
-    backward gives dL/dcentres through mfs_solve_backward (adjoint GMRES and
-    the backward pair sums).  ``spec`` is a dict with the plan's fixed inputs:
-    precision, sys_body_ptr, sys_kind, rot, shape_of_body, shape_src,
-    shape_trg, mu, net (device tensor), tol, max_iter."""
+    """out = solve(centres, net) for fixed shapes and rotations: rigid
+    velocities from forces and torques (Stokes) or potentials from charges
+    (Laplace).  backward gives dL/dcentres and dL/dnet through
+    mfs_gmres_solve_backward (adjoint GMRES, the backward pair sums and the
+    transposed pair sum of the right-hand side).  ``spec`` is a dict with the
+    plan's fixed inputs: precision, sys_body_ptr, sys_kind, rot, shape_of_body,
+    shape_src, shape_trg, mu, tol, max_iter.  A forward or adjoint solve that
+    ends above tol raises MfsError (MFS_NOT_CONVERGED)."""
 
     @staticmethod
-    def forward(ctx, centre: torch.Tensor, spec: dict):
+    def forward(ctx, centre: torch.Tensor, net: torch.Tensor, spec: dict):
         plan = Plan(spec["precision"], spec["sys_body_ptr"], spec["sys_kind"], centre.detach().cpu().numpy(),
                     spec["rot"], spec["shape_of_body"], spec["shape_src"], spec["shape_trg"], spec.get("mu", 1.0),
                     device=centre.device)
-        out, info = plan.solve(spec["net"], tol=spec.get("tol", 1e-5), max_iter=spec.get("max_iter", 200))
-        ctx.plan, ctx.info, ctx.spec = plan, info, spec
+        b, s0 = plan.rhs(net.detach().contiguous())
+        gamma, _, _, _ = plan.gmres_solve(b, spec.get("tol", 1e-5), spec.get("max_iter", 200),
+                                          raise_not_converged=True)
+        out, _ = plan.extract(gamma, s0)
+        ctx.plan, ctx.gamma, ctx.s0, ctx.spec = plan, gamma, s0, spec
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        g, _, _, _ = ctx.plan.solve_backward(ctx.info["gamma"], ctx.info["s0"], grad_out.contiguous(),
-                                             tol=ctx.spec.get("tol", 1e-5), max_iter=ctx.spec.get("max_iter", 200))
-        return g, None
+        gc, gn, _, _, _ = ctx.plan.gmres_solve_backward(
+            ctx.gamma, ctx.s0, grad_out.contiguous(), tol=ctx.spec.get("tol", 1e-5),
+            max_iter=ctx.spec.get("max_iter", 200), want_centre=ctx.needs_input_grad[0],
+            want_net=ctx.needs_input_grad[1], raise_not_converged=True)
+        return gc, gn, None

@@ -28,7 +28,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("mfs_p2p_stokes", "mfs_p2p_laplace", "mfs_precond_apply", "mfs_matvec", "mfs_gmres_solve",
-                 "mfs_p2p_stokes_backward", "mfs_p2p_laplace_backward", "mfs_solve_backward"):
+                 "mfs_p2p_stokes_backward", "mfs_p2p_laplace_backward", "mfs_gmres_solve_backward"):
         assert must in names
 
 

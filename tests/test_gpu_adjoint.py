@@ -1,5 +1,6 @@
-"""Gradients of a mobility loss with respect to the particle centres: the
-adjoint solve (mfs_solve_backward, the backward pair kernels, the adjoint
+"""Gradients of a mobility loss with respect to the particle centres and the
+given net quantities: the
+adjoint solve (mfs_gmres_solve_backward, the backward pair kernels, the adjoint
 matvec) against the oracle's adjoint gradient and against central finite
 differences of forward solves.
 
@@ -37,7 +38,7 @@ def _gpu_grad(wl, prec, tol):
     mfs = _mfs()
     plan = mfs.Plan.from_workload(wl, prec)
     out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
-    g, iters, relres, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+    g, _, iters, relres, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
     assert st == mfs.MFS_OK
     U = out.cpu().numpy().reshape(-1, 6)
     return float(np.sum(U * U)), g.cpu().numpy(), iters
@@ -68,15 +69,48 @@ def test_gradient_ellipsoids_matches_oracle():
 def test_autograd_function():
     mfs = _mfs()
     wl = W.small_cluster(3, W.STOKES, 60, 130, seed=33, axes=(1.0, 1.0, 1.0))
-    _, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    _, g_ref, info = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
     spec = dict(precision=mfs.MIXED, sys_body_ptr=wl.sys_body_ptr, sys_kind=wl.sys_kind, rot=wl.rot,
                 shape_of_body=wl.shape_of_body, shape_src=[s.src for s in wl.shapes],
-                shape_trg=[s.trg for s in wl.shapes], mu=1.0, net=_dev(net_flat(wl)), tol=1e-8)
+                shape_trg=[s.trg for s in wl.shapes], mu=1.0, tol=1e-8)
     centre = torch.tensor(wl.centre, dtype=torch.float64, device="cuda", requires_grad=True)
-    U = mfs.MobilitySolve.apply(centre, spec)
+    net = _dev(net_flat(wl)).requires_grad_(True)
+    U = mfs.MobilitySolve.apply(centre, net, spec)
     loss = (U * U).sum()
     loss.backward()
+    print("autograd: centre grad err", rel_inf(centre.grad.cpu().numpy(), g_ref),
+          "net grad err", rel_inf(net.grad.cpu().numpy(), info["grad_net"].reshape(-1)))
     assert rel_inf(centre.grad.cpu().numpy(), g_ref) <= 1e-5
+    assert rel_inf(net.grad.cpu().numpy(), info["grad_net"].reshape(-1)) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_net_gradient_matches_oracle(kind):
+    """dJ/d(net) (forces and torques, or charges) of J = sum |U|^2 or sum phi^2
+    from mfs_gmres_solve_backward against the oracle's (itself pinned by
+    central differences of whole solves in the net quantities), together with
+    the centre gradient from the same call; NULL strength0 with a centre
+    gradient requested is refused."""
+    mfs = _mfs()
+    wl = W.small_cluster(4, kind, 45, 301, seed=35)
+    _, g_ref, info_ref = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    gn_ref = info_ref["grad_net"].reshape(-1)
+    for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-8, 1e-5)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
+        gc, gn, iters, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol,
+                                                         want_net=True)
+        assert st == mfs.MFS_OK
+        e = (rel_inf(gc.cpu().numpy(), g_ref), rel_inf(gn.cpu().numpy(), gn_ref))
+        print(f"kind={kind} prec={prec} centre grad err {e[0]:.2e} net grad err {e[1]:.2e} iters {iters}")
+        assert max(e) <= bar
+        _, gn2, _, _, st = plan.gmres_solve_backward(info["gamma"], None, 2.0 * out, tol=tol, want_centre=False,
+                                                     want_net=True)
+        assert st == mfs.MFS_OK and rel_inf(gn2.cpu().numpy(), gn.cpu().numpy()) <= 1e-12
+        with pytest.raises(mfs.MfsError) as err:
+            plan.gmres_solve_backward(info["gamma"], None, 2.0 * out, tol=tol)
+        assert err.value.status == mfs.MFS_EINVAL
+        plan.close()
 
 
 @pytest.mark.timeout(600)
@@ -120,7 +154,7 @@ def test_elastance_gradient_matches_oracle():
     for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-8, 1e-5)):
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
-        g, iters, relres, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+        g, _, iters, relres, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
         assert st == mfs.MFS_OK
         J = float((out * out).sum())
         e = rel_inf(g.cpu().numpy(), g_ref)

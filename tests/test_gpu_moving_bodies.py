@@ -119,7 +119,7 @@ def test_gradient_step_by_moving_bodies():
 
     def loss_and_grad():
         out, info = plan.solve(net, tol=1e-12)
-        g, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=1e-12)
+        g, _, _, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=1e-12)
         assert st == mfs.MFS_OK
         return float((out * out).sum()), g.cpu().numpy()
 

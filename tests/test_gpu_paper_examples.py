@@ -1,4 +1,4 @@
-"""The paper's small elastance test (Section 6) at its own sizes on the GPU:
+"""The paper's small elastance test (Section 4.1) at its own sizes on the GPU:
 10 unit spheres grown compactly at delta = 0.1, R_p = 0.7, N = 969, M = 1123,
 GMRES tolerance 1e-8 (values in tests/golden/paper_elastance_spheres.txt).
 
@@ -69,7 +69,7 @@ def test_paper_elastance_example_on_gpu():
 @pytest.mark.parametrize("delta", [0.2, 0.5])
 def test_two_spheres_exact_on_gpu(delta):
     """Two unit spheres, equal forces along the line of centres (the paper's
-    two-sphere comparison setting, Section 7): GPU velocities against the exact
+    two-sphere comparison setting, Appendix A.1): GPU velocities against the exact
     Stimson-Jeffery solution.  N = 800, M = 1600: FP64 within 1e-8 (the MFS
     discretisation error here is 4e-10), mixed at tol 1e-7 within 1e-6."""
     from tests._helpers import stimson_jeffery_lambda, two_sphere_workload

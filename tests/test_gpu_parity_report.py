@@ -140,7 +140,7 @@ def _rows(kind):
     for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(net, tol=tol)
-        gc, _, _, st = plan.solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
+        gc, _, _, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
         assert st == mfs.MFS_OK
         add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
         plan.close()

@@ -69,7 +69,7 @@ def test_resistance_operator_and_solve(kind):
         print(kind, prec, "solve out, lambda", e, "iters", info["iters"], "oracle iters", sol["iters"])
         assert e[0] <= bar
         with pytest.raises(mfs.MfsError) as err:
-            plan.solve_backward(info["gamma"], info["s0"], out, tol=1e-8)
+            plan.gmres_solve_backward(info["gamma"], info["s0"], out, tol=1e-8)
         assert err.value.status == mfs.MFS_EUNSUPPORTED
         plan.close()
 

@@ -608,7 +608,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
 
 # ---------------------------------------------------------------------------
-# the paper's small elastance test (Section 6): printed values in tests/golden/
+# the paper's small elastance test (Section 4.1): printed values in tests/golden/
 # ---------------------------------------------------------------------------
 
 def _paper_elastance():
@@ -647,7 +647,7 @@ def test_paper_elastance_example():
 
 # ---------------------------------------------------------------------------
 # two spheres: the exact Stimson-Jeffery solution (the two-sphere setting of
-# the paper's comparison with spherical-harmonic solvers, Section 7)
+# the paper's comparison with spherical-harmonic solvers, Appendix A.1)
 # ---------------------------------------------------------------------------
 
 def test_two_spheres_along_the_line_of_centres_exact():
