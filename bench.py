@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_PAIR = {1: 28.0, 0: 11.0}      # Stokes, Laplace (FMA = 2, rsqrt = 1)
 PEAK_FP32_TFLOPS = 157.3                  # MI355X FP32 vector peak (published)
+STOP_FACTOR = 0.1                         # the library's default GMRES stopping margin
 WORKLOADS = ("ellipsoids_100", "ellipsoids_1000", "batched_64", "spheres_200_grad", "ellipsoids_100_2way",
              "ellipsoids_10000")
 # minutes-long solves: one step, no warm-up, no autotuning, no separate FP64 solve, progress lines
@@ -79,13 +80,19 @@ def _pairs_per_system(wl):
     return out
 
 
-def _counter_traffic(workload: str, shape):
+def _counter_file(workload: str, kind: int) -> str:
+    if workload == "batched_64":
+        return os.path.join(ROOT, "profiles", "p2p_mixed_batched_64_pmc.txt")
+    return os.path.join(ROOT, "profiles", f"p2p_mixed_{'stokes' if kind else 'laplace'}_{workload}_pmc.txt")
+
+
+def _counter_traffic(workload: str, kind: int, shape):
     """HBM bytes per launch of the pair kernel at launch shape `shape` (targets
     per lane, work items, persistent) from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (copy-kernel calibrated), or None when the kernel source
-    has changed since the counters were taken."""
+    WRITE_SIZE summary (copy-kernel calibrated), or None when there is none for
+    this workload or the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"p2p_mixed_stokes_{workload}_pmc.txt")
+    path = _counter_file(workload, kind)
     src = os.path.join(ROOT, "paper_2409_04215_amd", "csrc", "p2p_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -102,6 +109,103 @@ def _counter_traffic(workload: str, shape):
     return None
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+STORED = {("ellipsoids_100", 1): "ellipsoids_100_stokes_U.txt", ("ellipsoids_100", 0): "ellipsoids_100_laplace_phi.txt",
+          ("ellipsoids_1000", 1): "ellipsoids_1000_stokes_U.txt", ("ellipsoids_1000", 0): "ellipsoids_1000_laplace_phi.txt"}
+
+
+def _stored_oracle(workload: str, kind: int, wl):
+    """Stored FP64 oracle outputs of this workload (GMRES tol 1e-10, written by
+    tests/golden/make_golden.py): a list of (system, reference (P_s, 6) or (P_s,)),
+    empty when none are stored."""
+    import numpy as np
+    if workload == "batched_64":
+        path = os.path.join(GOLDEN, "batched_64_subset.txt")
+        if not os.path.exists(path):
+            return []
+        tab = np.loadtxt(path, ndmin=2)
+        out = []
+        for sy in sorted(set(tab[:, 0].astype(int))):
+            rows = tab[tab[:, 0] == sy]
+            out.append((sy, rows[:, 2:8] if wl.sys_kind[sy] == 1 else rows[:, 2]))
+        return out
+    name = STORED.get((workload, kind))
+    if name is None or not os.path.exists(os.path.join(GOLDEN, name)):
+        return []
+    return [(0, np.loadtxt(os.path.join(GOLDEN, name)).reshape(wl.n_body, -1).squeeze())]
+
+
+def _vs_oracle(out, wl, stored):
+    """Largest per-system rel_inf = max|out - ref| / max|ref| over the stored
+    systems, separately for rigid velocities and potentials."""
+    import numpy as np
+    if not stored:
+        return None
+    dims = [6 if k == 1 else 1 for k in wl.sys_kind]
+    offs = np.concatenate([[0], np.cumsum([dims[sy] * (wl.sys_body_ptr[sy + 1] - wl.sys_body_ptr[sy])
+                                           for sy in range(wl.n_sys)])]).astype(np.int64)
+    o = out.detach().cpu().numpy()
+    res = {"systems": len(stored), "bodies": int(sum(len(r) for _, r in stored))}
+    for sy, ref in stored:
+        got = o[offs[sy]:offs[sy + 1]].reshape(ref.shape)
+        key = "stokes_U" if wl.sys_kind[sy] == 1 else "laplace_phi"
+        res[key] = max(res.get(key, 0.0), float(np.abs(got - ref).max() / np.abs(ref).max()))
+    return res
+
+
+def _kind_subset(wl, kind):
+    """Points and structure of the systems of one kind (for the standalone pair sums)."""
+    import numpy as np
+    X, _ = wl.world_points("trg")
+    Y, _ = wl.world_points("src")
+    n_trg = np.array([wl.shapes[i].trg.shape[0] for i in wl.shape_of_body])
+    n_src = np.array([wl.shapes[i].src.shape[0] for i in wl.shape_of_body])
+    t_off = np.concatenate([[0], np.cumsum(n_trg)])
+    s_off = np.concatenate([[0], np.cumsum(n_src)])
+    sys_ptr, bodies = [0], []
+    for sy in range(wl.n_sys):
+        if wl.sys_kind[sy] == kind:
+            b0, b1 = int(wl.sys_body_ptr[sy]), int(wl.sys_body_ptr[sy + 1])
+            bodies += list(range(b0, b1))
+            sys_ptr.append(len(bodies))
+    if not bodies:
+        return None
+    bodies = np.array(bodies)
+    xi = np.concatenate([np.arange(t_off[b], t_off[b + 1]) for b in bodies])
+    yi = np.concatenate([np.arange(s_off[b], s_off[b + 1]) for b in bodies])
+    return (np.array(sys_ptr, np.int64), np.concatenate([[0], np.cumsum(n_trg[bodies])]).astype(np.int64),
+            np.concatenate([[0], np.cumsum(n_src[bodies])]).astype(np.int64), X[xi], Y[yi])
+
+
+def standalone_p2p(mfs, torch, np, wl, per_sys, reps: int = 5):
+    """The standalone pair sums (mfs_p2p_stokes, mfs_p2p_laplace; mixed, off-body
+    pairs) on the workload's own points, one call per PDE kind over all its
+    systems: HIP events on the calling stream around `reps` calls after one
+    untimed call (which builds the cached work tables)."""
+    res = {}
+    for kind, fn in ((1, mfs.p2p_stokes), (0, mfs.p2p_laplace)):
+        sub = _kind_subset(wl, kind)
+        if sub is None:
+            continue
+        sp, tp, pp, X, Y = sub
+        dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+        x, y = dev(X), dev(Y)
+        st = dev(np.random.default_rng(5).standard_normal((Y.shape[0], 3) if kind else Y.shape[0]))
+        out = torch.empty((X.shape[0], 3) if kind else X.shape[0], dtype=torch.float64, device="cuda")
+        fn(sp, tp, pp, x, y, st, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(sp, tp, pp, x, y, st, out=out)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pairs = sum(off for k, off, _ in per_sys if k == kind)
+        res["stokes" if kind else "laplace"] = {"ms_per_call": round(ms, 4), "ginter_s": round(pairs / (ms * 1e-3) / 1e9, 2),
+                                                "off_body_pairs": pairs}
+    return res
+
+
 def _timed_solves(plan, net, tol, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -115,6 +219,29 @@ def _timed_solves(plan, net, tol, steps, torch):
 
 
 def cpu_baseline(wl, budget_s: float = 15.0):
+    """The oracle's FP64 matvec on a bounded sample of the workload: for one
+    suspension the whole budget goes to it; for several (batched_64), half the
+    budget each to the largest Stokes and the largest Laplace system, and the
+    rate is their pairs over their summed time."""
+    if wl.n_sys == 1:
+        return _cpu_baseline_one(wl, budget_s)
+    sizes = [int(wl.sys_body_ptr[sy + 1] - wl.sys_body_ptr[sy]) for sy in range(wl.n_sys)]
+    picks = []
+    for kind in (1, 0):
+        idx = [sy for sy in range(wl.n_sys) if wl.sys_kind[sy] == kind]
+        if idx:
+            picks.append(max(idx, key=lambda sy: sizes[sy]))
+    parts = [_cpu_baseline_one(wl.system(sy), budget_s / len(picks)) for sy in picks]
+    pairs = sum(p["pairs"] for p in parts)
+    dt = sum(p["seconds"] for p in parts)
+    out = dict(parts[0])
+    out.update(value=pairs / dt / 1e9, seconds=dt, pairs=pairs,
+               sample="; ".join(f"system {sy} ({sizes[sy]} bodies, {'Stokes' if wl.sys_kind[sy] else 'Laplace'}): "
+                                f"{p['sample']}" for sy, p in zip(picks, parts)))
+    return out
+
+
+def _cpu_baseline_one(wl, budget_s: float = 15.0):
     """The oracle's matvec (FP64, plain C pair loops on all host threads plus
     numpy pseudo-inverse blocks), timed for about budget_s seconds: whole
     matvecs when one fits in the budget, else one matvec restricted to a
@@ -164,7 +291,7 @@ def cpu_baseline(wl, budget_s: float = 15.0):
                   f"rows (all {len(pr.bodies)} pseudo-inverse blocks + those rows' off-body pair sums), "
                   f"{dt:.1f} s")
     return dict(value=pairs / dt / 1e9, unit="Ginteractions/s", cores=O.oracle_threads(), kind="oracle",
-                sample=sample + "; off-body pairs per second of that work", seconds=dt,
+                sample=sample + "; off-body pairs per second of that work", seconds=dt, pairs=pairs,
                 host_cpu=_cpu_model(), host_logical_cpus=os.cpu_count())
 
 
@@ -290,7 +417,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 5; 1 for the 10^4 case)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; 0 for the 10^4 case)")
-    ap.add_argument("--workload", default="ellipsoids_100", choices=WORKLOADS)
+    ap.add_argument("--workload", default="batched_64", choices=WORKLOADS,
+                    help="default: batched_64, the largest single-GPU configuration (64 suspensions, 6917 bodies)")
     ap.add_argument("--kind", default="stokes", choices=("stokes", "laplace"),
                     help="PDE of the ellipsoid workloads (batched_64 mixes both; spheres_200_grad is Stokes)")
     ap.add_argument("--tol", type=float, default=1e-5)
@@ -408,11 +536,12 @@ def main():
         plan_mx.set_graph(True)
         step(plan_mx)
         torch.cuda.synchronize()
+        n_graph = min(args.steps, 3)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(n_graph):
             step(plan_mx)
         torch.cuda.synchronize()
-        graph_s = (time.perf_counter() - t0) / args.steps
+        graph_s = (time.perf_counter() - t0) / n_graph
         plan_mx.set_graph(False)
 
     fp64_s = diff = None
@@ -431,6 +560,28 @@ def main():
         plan_64.set_timing(False)
         diff = float((out_mx - out_64).abs().max() / out_64.abs().max())
     extra = {}
+    stored = _stored_oracle(args.workload, kind, wl)
+    if stored:
+        extra["rel_inf_vs_oracle_mixed"] = _vs_oracle(out_mx, wl, stored)
+        if info_64 is not None:
+            extra["rel_inf_vs_oracle_fp64"] = _vs_oracle(out_64, wl, stored)
+    if not large:
+        # the same mixed solve under the stopping rule as the paper states it (stop once the
+        # residual estimate is below tol): fewer iterations, larger output error
+        plan_mx.set_stop_factor(1.0)
+        step(plan_mx)
+        torch.cuda.synchronize()
+        n_s1 = min(args.steps, 3)
+        t0 = time.perf_counter()
+        for _ in range(n_s1):
+            out_s1, info_s1, _, _, _, its_s1 = step(plan_mx)
+        torch.cuda.synchronize()
+        extra["stop_factor_1"] = {"solve_time_mixed_s": round((time.perf_counter() - t0) / n_s1, 5),
+                                  "max_iters": int(np.max(its_s1)),
+                                  "rel_inf_vs_oracle": _vs_oracle(out_s1, wl, stored) if stored else None}
+        plan_mx.set_stop_factor(STOP_FACTOR)
+    if not large:
+        extra["p2p_standalone_mixed"] = standalone_p2p(mfs, torch, np, wl, per_sys)
     # moving the bodies of the resident plan (same positions here) against building a new one:
     # the one-body factors are kept, only the geometry is rebuilt
     t_mv = time.perf_counter()
@@ -464,8 +615,7 @@ def main():
                             "with an FMM in under two hours")
 
     shape = (abs(tuned[0]), tuned[1], int(tuned[0] < 0)) if tuned else (1, 2048, 0)
-    traffic = (_counter_traffic(args.workload, shape)
-               if args.workload == "ellipsoids_100" and kind == 1 else None)
+    traffic = _counter_traffic(args.workload, kind, shape)
     avg_ms = ms_mx / max(n_mx, 1)
     achieved = tot_flops / (ms_mx * 1e-3) / 1e12 if ms_mx > 0 else 0.0
     flops_per_pair = tot_flops / max(tot_pairs_mx, 1.0)
@@ -489,7 +639,9 @@ def main():
                    "proxies_per_body": int(wl.shapes[0].src.shape[0]),
                    "collocation_per_body": int(wl.shapes[0].trg.shape[0]),
                    "kernel": " + ".join(kind_name[k] for k in kinds) + (" + centre gradient" if grad else ""),
-                   "gmres_tol": args.tol, "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total,
+                   "gmres_tol": args.tol,
+                   "gmres_stop": f"estimate <= {STOP_FACTOR}*tol (mfs_plan_set_stop_factor), then FP64 true residual <= tol",
+                   "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total,
                    "factorization": args.factorization},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -508,7 +660,7 @@ def main():
         "iters_per_system_last_step": [int(x) for x in np.asarray(its).reshape(-1)][:128],
         "relres_mixed_true_fp64_max": float(np.max(info_mx["relres"])),
         "relres_fp64_max": float(np.max(info_64["relres"])) if info_64 else None,
-        "p2p_kernel_ginter_s_mixed": round(ppl * n_mx / (ms_mx * 1e-3) / 1e9, 2) if ms_mx > 0 and wl.n_sys == 1 else None,
+        "p2p_kernel_ginter_s_mixed": round(tot_pairs_mx / (ms_mx * 1e-3) / 1e9, 2) if ms_mx > 0 else None,
         "p2p_kernel_ginter_s_fp64": round(ppl * n64 / (ms64 * 1e-3) / 1e9, 2) if ms64 > 0 and wl.n_sys == 1 else None,
         "rel_diff_out_mixed_vs_fp64_gpu": diff,
         "setup_s": round(setup_s, 3),
@@ -517,7 +669,7 @@ def main():
         **extra,
     }
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl.system(0) if wl.n_sys > 1 else wl)
+        rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -91,9 +91,15 @@ const char *mfs_version(void);
  * Data arrays [device]: trg_xyz [n_trg][3], src_xyz [n_src][3],
  *   src_q [n_src] / src_f [n_src][3], out_u [n_trg] / [n_trg][3].
  * prec: MFS_MIXED or MFS_FP64.  mu must be finite and positive.
- * Uses a library-owned device workspace (allocated on first use, grown as
- * needed).  Errors: MFS_EINVAL for NULL data pointers, n_sys < 1, bad
- * structure arrays, unknown flags or precision.
+ * Asynchronous on `stream`.  Uses a library-owned device workspace, one per
+ * host thread and device (allocated on first use; growing it waits for the
+ * device).  The first call with a given structure (the three pointer arrays,
+ * mu and the entry point) also builds the work tables of its launch and keeps
+ * them for later calls with the same structure (up to 8 structures per
+ * workspace; evicting one waits for the device).  Calls of one host thread on
+ * different streams share that workspace and must not overlap.
+ * Errors: MFS_EINVAL for NULL data pointers, n_sys < 1, bad structure arrays,
+ * unknown flags or precision.
  * ------------------------------------------------------------------------- */
 int mfs_p2p_laplace(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
                     const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
@@ -271,7 +277,8 @@ int mfs_matvec_adjoint(mfs_plan plan, const double *w, double *out, int prec, vo
  * the GPU does not wait for it (with a progress callback set it reads every
  * status first; the results are the same).
  * Every system stops on its own when ||r||_2 <= tol ||b||_2 (the iteration
- * aims at tol/2, a margin for the outputs' error).  With a MIXED
+ * aims at stop_factor * tol, a margin for the outputs' error; see
+ * mfs_plan_set_stop_factor).  With a MIXED
  * plan the Krylov matvec is the mixed one; each attempt ends with an FP64
  * true-residual matvec, and systems above tol restart from their iterate on
  * that residual (iterative refinement, at most max_refine restarts).
@@ -363,6 +370,16 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * ([host] outputs, may be NULL; *best_tpl is negative for the persistent
  * grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
+/* Stopping margin of mfs_gmres_solve (and of the adjoint solve of
+ * mfs_gmres_solve_backward): GMRES iterates until its residual estimate is at
+ * most factor * tol * ||b||_2 per system (Section 4: GMRES with a relative
+ * tolerance; factor 1 is that rule as stated), and a solve succeeds when the
+ * final relative residual (the FP64 true one for MIXED plans) is at most tol.
+ * The relative residual bounds the outputs' error only up to the conditioning
+ * of the recovery, so the default, 0.1, keeps U and phi within tol of the
+ * exact discrete solution on the benchmark suspensions.  MFS_EINVAL unless
+ * 0 < factor <= 1. */
+int mfs_plan_set_stop_factor(mfs_plan plan, double factor);
 /* Progress of long solves.  With a callback set, mfs_gmres_solve (and the
  * adjoint solve of mfs_gmres_solve_backward) calls it on the calling host thread
  * after every GMRES iteration with: the matvecs spent so far (largest over

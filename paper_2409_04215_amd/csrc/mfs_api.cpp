@@ -59,14 +59,12 @@ static int upload_vec(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // pair-sum work items
 // ---------------------------------------------------------------------------
-int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
-                    const int64_t *body_src_ptr, const int64_t *out_ptr, const int32_t *kind_of_body, double mu,
-                    int tpl, int min_items, hipStream_t s) {
-    pp.items.clear();
-    pp.tpl = tpl;
+// Shape of a pair-sum launch: bodies per source chunk (the largest chunk, so the
+// fewest split slices, that still gives at least min_items items), the number of
+// split slices and the number of items.
+void p2p_item_count(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr, int tpl,
+                    int min_items, int64_t *chunk_out, int *n_split_out, int64_t *n_items_out) {
     const int blk = 64 * tpl;  // targets per item: 64 lanes x tpl (the pair kernels' item shape)
-    // bodies per source chunk: the largest chunk (fewest split slices) that still
-    // gives at least min_items items.
     auto count_items = [&](int64_t chunk) {
         int64_t n = 0;
         for (int64_t sy = 0; sy < n_sys; ++sy) {
@@ -84,15 +82,39 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
     int n_split = 1;
     for (int64_t sy = 0; sy < n_sys; ++sy)
         n_split = std::max(n_split, (int)((sys_body_ptr[sy + 1] - sys_body_ptr[sy] + chunk - 1) / chunk));
-    struct Work { P2PItem it; double w; };
-    std::vector<Work> work;
+    // every system writes all n_split slices
+    int64_t n = 0;
+    for (int64_t sy = 0; sy < n_sys; ++sy) {
+        const int64_t b0 = sys_body_ptr[sy], b1 = sys_body_ptr[sy + 1];
+        if (b1 == b0) continue;
+        const int64_t nt = body_trg_ptr[b1] - body_trg_ptr[b0];
+        n += ((nt + blk - 1) / blk) * n_split;
+    }
+    *chunk_out = chunk;
+    *n_split_out = n_split;
+    *n_items_out = n;
+}
+
+int generate_p2p_items(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                       const int64_t *body_src_ptr, const int64_t *out_ptr, int out_dim,
+                       const int32_t *kind_of_body, int kind_all, double mu, int tpl, int min_items, P2PItem *items,
+                       double *work, int32_t *order, P2PItem *sorted, int64_t cap, int64_t *n_items, int *n_split_out) {
+    const int blk = 64 * tpl;
+    int64_t chunk = 1, n = 0;
+    int n_split = 1;
+    p2p_item_count(n_sys, sys_body_ptr, body_trg_ptr, tpl, min_items, &chunk, &n_split, &n);
+
+    if (n > cap) return fail(MFS_EINVAL, "pair sum needs " + std::to_string(n) + " work items, more than " +
+                                             std::to_string(cap));
+    n = 0;
     for (int64_t sy = 0; sy < n_sys; ++sy) {
         const int64_t b0 = sys_body_ptr[sy], b1 = sys_body_ptr[sy + 1];
         if (b1 == b0) continue;
         const int64_t T0 = body_trg_ptr[b0], T1 = body_trg_ptr[b1];
-        const int kind = kind_of_body[b0];
+        const int kind = kind_of_body ? kind_of_body[b0] : kind_all;
         const double scale = kind == MFS_STOKES ? 1.0 / (8.0 * PI * mu) : 1.0 / (4.0 * PI);
         const int dim = kind == MFS_STOKES ? 3 : 1;
+        const int64_t base = out_ptr ? out_ptr[b0] : (int64_t)out_dim * body_trg_ptr[b0];
         for (int64_t t0 = T0; t0 < T1; t0 += blk) {
             const int64_t t1 = std::min(t0 + blk, T1);
             // every system writes all n_split slices (splits past its last body get an
@@ -100,7 +122,7 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
             for (int sp = 0; sp < n_split; ++sp) {
                 const int64_t c0 = std::min(b1, b0 + (int64_t)sp * chunk), c1 = std::min(b1, c0 + chunk);
                 P2PItem it{};
-                it.out0 = out_ptr[b0] + dim * (t0 - T0);
+                it.out0 = base + dim * (t0 - T0);
                 it.scale = scale;
                 it.t0 = (int32_t)t0;
                 it.t1 = (int32_t)t1;
@@ -110,14 +132,37 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
                 it.split = sp;
                 it.kind = kind;
                 const double nsrc = (double)(body_src_ptr[c1] - body_src_ptr[c0]);
-                work.push_back({it, nsrc * (double)(t1 - t0) * (kind == MFS_STOKES ? 2.5 : 1.0)});
+                items[n] = it;
+                work[n] = nsrc * (double)(t1 - t0) * (kind == MFS_STOKES ? 2.5 : 1.0);
+                order[n] = (int32_t)n;
+                ++n;
             }
         }
     }
-    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.w > b.w; });
-    pp.items.reserve(work.size());
-    for (auto &w : work) pp.items.push_back(w.it);
-    pp.n_split = n_split;
+    // largest work first (ties in generation order), so the dispatcher schedules greedily
+    std::sort(order, order + n, [&](int32_t a, int32_t b) { return work[a] > work[b] || (work[a] == work[b] && a < b); });
+    for (int64_t i = 0; i < n; ++i) sorted[i] = items[order[i]];
+    *n_items = n;
+    *n_split_out = n_split;
+    return MFS_OK;
+}
+
+int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                    const int64_t *body_src_ptr, const int64_t *out_ptr, const int32_t *kind_of_body, double mu,
+                    int tpl, int min_items, hipStream_t s) {
+    pp.tpl = tpl;
+    int64_t chunk = 1, cap = 0;
+    int n_split = 1;
+    p2p_item_count(n_sys, sys_body_ptr, body_trg_ptr, tpl, min_items, &chunk, &n_split, &cap);
+    std::vector<P2PItem> tmp(std::max<int64_t>(1, cap));
+    std::vector<double> work(std::max<int64_t>(1, cap));
+    std::vector<int32_t> order(std::max<int64_t>(1, cap));
+    pp.items.assign(std::max<int64_t>(1, cap), P2PItem{});
+    int64_t n = 0;
+    MFS_TRY(generate_p2p_items(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr, 1, kind_of_body, 0, mu, tpl,
+                               min_items, tmp.data(), work.data(), order.data(), pp.items.data(), cap, &n,
+                               &pp.n_split));
+    pp.items.resize(n);
     if (!pp.items.empty()) MFS_TRY(upload_vec(pp.d_items, pp.items, s));
     MFS_TRY(pp.d_counter.reserve(sizeof(int)));
     return MFS_OK;
@@ -132,12 +177,42 @@ using namespace mfs;
 // ---------------------------------------------------------------------------
 namespace {
 
-struct Workspace {
-    DevBuf centre, trg_body, src_body, trg_ptr, src_ptr, trg_off, src_ops, partial, tmp;
+// The structure-dependent part of a standalone call: device copies of the body
+// pointers, per-point body ids and the pair-sum work items.  Built on the first
+// call with a given structure and reused by later calls with the same one.
+struct Layout {
+    int variant = 0;  // which entry point family and kernel (see layout())
+    uint64_t mu_bits = 0;
+    std::vector<int64_t> sys, trg, src;  // host copies of the structure arrays (the cache key)
+    std::vector<int32_t> trg32, src32;
+    DevBuf trg_ptr, src_ptr, trg_body, src_body;
+    P2PPlan pp;
+    uint64_t last_use = 0;
 };
+
+struct Workspace {
+    DevBuf centre, trg_off, src_ops, partial;
+    std::vector<std::unique_ptr<Layout>> layouts;
+    uint64_t clock = 0;
+};
+constexpr size_t kMaxLayouts = 8;
+
+// one workspace per host thread and device
 Workspace &workspace() {
-    static thread_local Workspace w;
-    return w;
+    static thread_local std::vector<std::unique_ptr<Workspace>> per_device;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if ((int)per_device.size() <= dev) per_device.resize(dev + 1);
+    if (!per_device[dev]) per_device[dev] = std::make_unique<Workspace>();
+    return *per_device[dev];
+}
+
+// Standalone calls are asynchronous, so a workspace buffer may still be read by
+// work enqueued earlier: wait for the device before a buffer is replaced.
+int grow(DevBuf &b, size_t n) {
+    if (n <= b.bytes && b.ptr) return MFS_OK;
+    if (b.ptr) MFS_HIP_TRY(hipDeviceSynchronize());
+    return b.reserve(n);
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -167,23 +242,89 @@ int check_prec(int prec) {
     return MFS_OK;
 }
 
-// Sets up the split representation of standalone FP64 inputs in the workspace.
-int standalone_geometry(Workspace &ws, int64_t n_body, int64_t n_trg, int64_t n_src, const int64_t *body_trg_ptr,
-                        const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, int prec,
-                        hipStream_t s) {
-    std::vector<int32_t> tp(body_trg_ptr, body_trg_ptr + n_body + 1), sp(body_src_ptr, body_src_ptr + n_body + 1);
-    MFS_TRY(upload_vec(ws.trg_ptr, tp, s));
-    MFS_TRY(upload_vec(ws.src_ptr, sp, s));
-    MFS_TRY(ws.centre.reserve(std::max<int64_t>(1, n_body) * 3 * sizeof(double)));
-    MFS_TRY(ws.trg_body.reserve(std::max<int64_t>(1, n_trg) * sizeof(int32_t)));
-    MFS_TRY(ws.src_body.reserve(std::max<int64_t>(1, n_src) * sizeof(int32_t)));
-    MFS_TRY(launch_body_refpoint(n_body, ws.src_ptr.as<int32_t>(), ws.trg_ptr.as<int32_t>(), src_xyz, trg_xyz,
+// The cached layout of (variant, mu, structure), built if missing.  kind sets
+// the items' kernel and scale; dim the output values per target of the items.
+int layout(Workspace &ws, int variant, int kind, int dim, double mu, int64_t n_sys, const int64_t *sys_body_ptr,
+           const int64_t *body_trg_ptr, const int64_t *body_src_ptr, int64_t nb, hipStream_t s, Layout **out) {
+    uint64_t bits;
+    std::memcpy(&bits, &mu, sizeof bits);
+    auto same = [&](const Layout &l) {
+        return l.variant == variant && l.mu_bits == bits && (int64_t)l.sys.size() == n_sys + 1 &&
+               (int64_t)l.trg.size() == nb + 1 && (int64_t)l.src.size() == nb + 1 &&
+               std::equal(l.sys.begin(), l.sys.end(), sys_body_ptr) &&
+               std::equal(l.trg.begin(), l.trg.end(), body_trg_ptr) &&
+               std::equal(l.src.begin(), l.src.end(), body_src_ptr);
+    };
+    for (auto &l : ws.layouts)
+        if (same(*l)) {
+            l->last_use = ++ws.clock;
+            *out = l.get();
+            return MFS_OK;
+        }
+    if (ws.layouts.size() >= kMaxLayouts) {
+        // the evicted layout's items may still be read by enqueued work
+        MFS_HIP_TRY(hipDeviceSynchronize());
+        auto lru = std::min_element(ws.layouts.begin(), ws.layouts.end(),
+                                    [](const std::unique_ptr<Layout> &a, const std::unique_ptr<Layout> &b) {
+                                        return a->last_use < b->last_use;
+                                    });
+        ws.layouts.erase(lru);
+    }
+    auto l = std::make_unique<Layout>();
+    l->variant = variant;
+    l->mu_bits = bits;
+    l->sys.assign(sys_body_ptr, sys_body_ptr + n_sys + 1);
+    l->trg.assign(body_trg_ptr, body_trg_ptr + nb + 1);
+    l->src.assign(body_src_ptr, body_src_ptr + nb + 1);
+    l->trg32.assign(body_trg_ptr, body_trg_ptr + nb + 1);
+    l->src32.assign(body_src_ptr, body_src_ptr + nb + 1);
+    MFS_TRY(upload_vec(l->trg_ptr, l->trg32, s));
+    MFS_TRY(upload_vec(l->src_ptr, l->src32, s));
+    MFS_TRY(l->trg_body.reserve(std::max<int64_t>(1, body_trg_ptr[nb]) * sizeof(int32_t)));
+    MFS_TRY(l->src_body.reserve(std::max<int64_t>(1, body_src_ptr[nb]) * sizeof(int32_t)));
+    MFS_TRY(launch_fill_body_ids(nb, l->trg_ptr.as<int32_t>(), l->trg_body.as<int32_t>(), s));
+    MFS_TRY(launch_fill_body_ids(nb, l->src_ptr.as<int32_t>(), l->src_body.as<int32_t>(), s));
+    std::vector<int64_t> out_ptr(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
+    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
+    MFS_TRY(build_p2p_items(l->pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), mu, 1,
+                            2048, s));
+    l->last_use = ++ws.clock;
+    *out = l.get();
+    ws.layouts.push_back(std::move(l));
+    return MFS_OK;
+}
+
+// Per call: the body reference points (the first proxy of each body), the
+// targets' offsets from them and the source records with their strengths.
+int standalone_operands(Workspace &ws, const Layout &lay, int kind, int64_t n_body, int64_t n_trg, int64_t n_src,
+                        const double *trg_xyz, const double *src_xyz, const double *str, int prec, hipStream_t s,
+                        P2PLaunch &L) {
+    MFS_TRY(grow(ws.centre, std::max<int64_t>(1, n_body) * 3 * sizeof(double)));
+    MFS_TRY(grow(ws.trg_off, std::max<int64_t>(1, n_trg) * (prec == MFS_MIXED ? 16 : 32)));
+    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
+                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
+    MFS_TRY(grow(ws.src_ops, std::max<int64_t>(1, n_src) * rec));
+    MFS_TRY(launch_body_refpoint(n_body, lay.src_ptr.as<int32_t>(), lay.trg_ptr.as<int32_t>(), src_xyz, trg_xyz,
                                  ws.centre.as<double>(), s));
-    MFS_TRY(launch_fill_body_ids(n_body, ws.trg_ptr.as<int32_t>(), ws.trg_body.as<int32_t>(), s));
-    MFS_TRY(launch_fill_body_ids(n_body, ws.src_ptr.as<int32_t>(), ws.src_body.as<int32_t>(), s));
-    MFS_TRY(ws.trg_off.reserve(std::max<int64_t>(1, n_trg) * (prec == MFS_MIXED ? 16 : 32)));
-    MFS_TRY(launch_make_trg_off(n_trg, trg_xyz, ws.trg_body.as<int32_t>(), ws.centre.as<double>(), prec,
+    MFS_TRY(launch_make_trg_off(n_trg, trg_xyz, lay.trg_body.as<int32_t>(), ws.centre.as<double>(), prec,
                                 ws.trg_off.ptr, s));
+    MFS_TRY(launch_make_src(n_src, kind, src_xyz, lay.src_body.as<int32_t>(), ws.centre.as<double>(), str, prec,
+                            ws.src_ops.ptr, s));
+    L.prec = prec;
+    L.centre = ws.centre.as<double>();
+    L.trg_body = lay.trg_body.as<int32_t>();
+    L.src_ptr = lay.src_ptr.as<int32_t>();
+    L.trg_off = ws.trg_off.ptr;
+    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
+    return MFS_OK;
+}
+
+int standalone_partial(Workspace &ws, const Layout &lay, P2PLaunch &L) {
+    if (lay.pp.n_split > 1) {
+        MFS_TRY(grow(ws.partial, (size_t)lay.pp.n_split * L.n_val * sizeof(double)));
+        L.partial = ws.partial.as<double>();
+    }
     return MFS_OK;
 }
 
@@ -200,38 +341,17 @@ int p2p_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const i
     if (nt == 0) return MFS_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = workspace();
-    MFS_TRY(standalone_geometry(ws, nb, nt, ns, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, prec, s));
-    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
-                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
-    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
-    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), str, prec,
-                            ws.src_ops.ptr, s));
     const int dim = kind == MFS_STOKES ? 3 : 1;
-    std::vector<int64_t> out_ptr(nb + 1);
-    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
-    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
-    P2PPlan pp;
-    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), mu, 1,
-                            2048, s));
+    Layout *lay = nullptr;
+    MFS_TRY(layout(ws, kind, kind, dim, mu, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, nb, s, &lay));
     P2PLaunch L;
-    L.prec = prec;
+    MFS_TRY(standalone_operands(ws, *lay, kind, nb, nt, ns, trg_xyz, src_xyz, str, prec, s, L));
     L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
     L.accumulate = (flags & MFS_ACCUMULATE) != 0;
-    L.centre = ws.centre.as<double>();
-    L.trg_body = ws.trg_body.as<int32_t>();
-    L.src_ptr = ws.src_ptr.as<int32_t>();
-    L.trg_off = ws.trg_off.ptr;
-    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
     L.out = out;
     L.n_val = dim * nt;
-    if (pp.n_split > 1) {
-        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * L.n_val * sizeof(double)));
-        L.partial = ws.partial.as<double>();
-    }
-    MFS_TRY(launch_p2p(pp, L, s));
-    // pp.d_items must stay alive until the kernels have read it
-    MFS_HIP_TRY(hipStreamSynchronize(s));
-    return MFS_OK;
+    MFS_TRY(standalone_partial(ws, *lay, L));
+    return launch_p2p(lay->pp, L, s);
 }
 
 // Derived fields (pressure, traction, Laplace gradient) of standalone inputs.
@@ -248,38 +368,18 @@ int field_standalone(int field, int64_t n_sys, const int64_t *sys_body_ptr, cons
     if (nt == 0) return MFS_OK;
     hipStream_t s = (hipStream_t)stream;
     const int kind = field == MFS_FIELD_LAPLACE_GRADIENT ? MFS_LAPLACE : MFS_STOKES;
-    Workspace &ws = workspace();
-    MFS_TRY(standalone_geometry(ws, nb, nt, ns, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, prec, s));
-    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
-                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
-    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
-    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), str, prec,
-                            ws.src_ops.ptr, s));
     const int dim = field == MFS_FIELD_PRESSURE ? 1 : 3;
-    std::vector<int64_t> out_ptr(nb + 1);
-    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
-    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
-    P2PPlan pp;
-    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), 1.0, 1,
-                            2048, s));
+    Workspace &ws = workspace();
+    Layout *lay = nullptr;
+    MFS_TRY(layout(ws, 4 + field, kind, dim, 1.0, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, nb, s, &lay));
     P2PLaunch L;
-    L.prec = prec;
+    MFS_TRY(standalone_operands(ws, *lay, kind, nb, nt, ns, trg_xyz, src_xyz, str, prec, s, L));
     L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
     L.accumulate = (flags & MFS_ACCUMULATE) != 0;
-    L.centre = ws.centre.as<double>();
-    L.trg_body = ws.trg_body.as<int32_t>();
-    L.src_ptr = ws.src_ptr.as<int32_t>();
-    L.trg_off = ws.trg_off.ptr;
-    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
     L.out = out;
     L.n_val = dim * nt;
-    if (pp.n_split > 1) {
-        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * L.n_val * sizeof(double)));
-        L.partial = ws.partial.as<double>();
-    }
-    MFS_TRY(launch_field(field, pp, L, trg_normal, nt, s));
-    MFS_HIP_TRY(hipStreamSynchronize(s));
-    return MFS_OK;
+    MFS_TRY(standalone_partial(ws, *lay, L));
+    return launch_field(field, lay->pp, L, trg_normal, nt, s);
 }
 
 // Position gradient of the pairing over one orientation: lanes carry lane_vec
@@ -290,36 +390,17 @@ int p2p_grad_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, co
     const int64_t nb = sys_body_ptr[n_sys], nl = lane_ptr[nb], ns = src_ptr[nb];
     if (nl == 0) return MFS_OK;
     Workspace &ws = workspace();
-    MFS_TRY(standalone_geometry(ws, nb, nl, ns, lane_ptr, src_ptr, lane_xyz, src_xyz, prec, s));
-    const size_t rec = kind == MFS_STOKES ? (prec == MFS_MIXED ? sizeof(SrcS32) : sizeof(SrcS64))
-                                          : (prec == MFS_MIXED ? sizeof(SrcL32) : sizeof(SrcL64));
-    MFS_TRY(ws.src_ops.reserve(std::max<int64_t>(1, ns) * rec));
-    MFS_TRY(launch_make_src(ns, kind, src_xyz, ws.src_body.as<int32_t>(), ws.centre.as<double>(), src_str, prec,
-                            ws.src_ops.ptr, s));
     const int dim = kind == MFS_STOKES ? 3 : 1;
-    std::vector<int64_t> out_ptr(nb + 1);
-    for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * lane_ptr[b];
-    std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
-    P2PPlan pp;
-    MFS_TRY(build_p2p_items(pp, n_sys, sys_body_ptr, lane_ptr, src_ptr, out_ptr.data(), kob.data(), mu, 1, 2048, s));
+    Layout *lay = nullptr;
+    MFS_TRY(layout(ws, 8 + kind, kind, dim, mu, n_sys, sys_body_ptr, lane_ptr, src_ptr, nb, s, &lay));
     P2PLaunch L;
-    L.prec = prec;
+    MFS_TRY(standalone_operands(ws, *lay, kind, nb, nl, ns, lane_xyz, src_xyz, src_str, prec, s, L));
     L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
     L.accumulate = (flags & MFS_ACCUMULATE) != 0;
-    L.centre = ws.centre.as<double>();
-    L.trg_body = ws.trg_body.as<int32_t>();
-    L.src_ptr = ws.src_ptr.as<int32_t>();
-    L.trg_off = ws.trg_off.ptr;
-    (kind == MFS_STOKES ? L.srcS : L.srcL) = ws.src_ops.ptr;
     L.out = out_grad;
     L.n_val = 3 * nl;
-    if (pp.n_split > 1) {
-        MFS_TRY(ws.partial.reserve((size_t)pp.n_split * 3 * nl * sizeof(double)));
-        L.partial = ws.partial.as<double>();
-    }
-    MFS_TRY(launch_p2p_grad(pp, L, lane_vec, nl, s));
-    MFS_HIP_TRY(hipStreamSynchronize(s));
-    return MFS_OK;
+    MFS_TRY(standalone_partial(ws, *lay, L));
+    return launch_p2p_grad(lay->pp, L, lane_vec, nl, s);
 }
 
 int p2p_backward_standalone(int kind, int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
@@ -427,6 +508,7 @@ struct mfs_plan_s {
     double offbody_pairs = 0.0;
     // hipGraph replay of the GMRES matvec: captured once per (precision, direction)
     bool use_graph = false;
+    double stop_factor = 0.1;  // GMRES iterates until its estimate is below stop_factor * tol
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     DevBuf stage;  // fixed input buffer of the captured matvec
@@ -1620,12 +1702,12 @@ int gmres_solve_impl(mfs_plan p, const double *b, double *x, double tol, int max
     MFS_TRY(launch_fill(n, 0.0, x, s));
     double *r = p->R.as<double>();
     MFS_HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // both precisions aim at half the tolerance: the relative residual bounds the
-    // outputs' error only up to the conditioning, and the margin keeps them within
-    // tol of the exact solution on the benchmark suspensions (at 0.8 one 10-body
-    // system ended at 1.1 tol); for mixed plans the FP64 check then also passes
-    // without a restart (the GMRES estimate and the true residual agree to ~1e-7)
-    const double inner = 0.5;
+    // both precisions iterate until the residual estimate is below stop_factor * tol
+    // (mfs_plan_set_stop_factor): the relative residual bounds the outputs' error
+    // only up to the conditioning, and the margin keeps them within tol of the exact
+    // solution; for mixed plans the FP64 check then also passes without a restart
+    // (the GMRES estimate and the true residual agree to ~1e-7)
+    const double inner = p->stop_factor;
     for (int sy = 0; sy < S; ++sy) target[sy] = inner * tol * bn[sy];
     int status = MFS_OK;
     if (p->prec == MFS_FP64) {
@@ -1803,6 +1885,13 @@ extern "C" int mfs_plan_timing(mfs_plan p, int32_t prec, int32_t reset, int64_t 
 // ---------------------------------------------------------------------------
 // options: graphs and autotuning
 // ---------------------------------------------------------------------------
+extern "C" int mfs_plan_set_stop_factor(mfs_plan p, double factor) {
+    if (!p) return fail(MFS_EINVAL, "NULL plan");
+    if (!(factor > 0.0 && factor <= 1.0)) return fail(MFS_EINVAL, "stop factor must be in (0, 1]");
+    p->stop_factor = factor;
+    return MFS_OK;
+}
+
 extern "C" int mfs_plan_set_graph(mfs_plan p, int32_t enable) {
     if (!p) return fail(MFS_EINVAL, "NULL plan");
     p->use_graph = enable != 0;

@@ -129,8 +129,31 @@ int build_p2p_items(P2PPlan &pp, int64_t n_sys, const int64_t *sys_body_ptr, con
                     const int64_t *body_src_ptr, const int64_t *out_ptr, const int32_t *kind_of_body,
                     double mu, int tpl, int min_items, hipStream_t s);
 
+// The same items written into caller-provided host arrays, with no heap
+// allocation: out_ptr may be null (then out_dim * body_trg_ptr[b]) and
+// kind_of_body null (then every body has `kind`).  items, work and order need
+// room for cap entries; on return items[0..*n_items) are in launch order.
+// MFS_EINVAL when more than cap items would be needed.
+int generate_p2p_items(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                       const int64_t *body_src_ptr, const int64_t *out_ptr, int out_dim,
+                       const int32_t *kind_of_body, int kind, double mu, int tpl, int min_items, P2PItem *items,
+                       double *work, int32_t *order, P2PItem *sorted, int64_t cap, int64_t *n_items, int *n_split);
+
+// A pair-sum launch's items wherever they live (device pointers).
+struct P2PItems {
+    const P2PItem *items = nullptr;
+    int n_items = 0;
+    int n_split = 1;
+    int tpl = 1;
+    bool persistent = false;
+    int persistent_grid = 2048;
+    int *counter = nullptr;  // persistent mode only
+};
+P2PItems items_of(const P2PPlan &pp);
+
 // kernels (p2p_kernels.hip)
-int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s);
+int launch_p2p(const P2PItems &it, const P2PLaunch &L, hipStream_t s);
+inline int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) { return launch_p2p(items_of(pp), L, s); }
 
 // Standalone conversion: FP64 world points to the split representation.
 int launch_body_refpoint(int64_t n_body, const int32_t *src_ptr, const int32_t *trg_ptr, const double *src_xyz,

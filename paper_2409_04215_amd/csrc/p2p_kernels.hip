@@ -470,10 +470,22 @@ __global__ void make_src_kernel(int64_t n, int kind, const double *__restrict__ 
 
 }  // namespace
 
-int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) {
-    if (pp.items.empty()) return MFS_OK;
+P2PItems items_of(const P2PPlan &pp) {
+    P2PItems it;
+    it.items = pp.d_items.as<P2PItem>();
+    it.n_items = (int)pp.items.size();
+    it.n_split = pp.n_split;
+    it.tpl = pp.tpl;
+    it.persistent = pp.persistent;
+    it.persistent_grid = pp.persistent_grid;
+    it.counter = pp.d_counter.as<int>();
+    return it;
+}
+
+int launch_p2p(const P2PItems &pp, const P2PLaunch &L, hipStream_t s) {
+    if (pp.n_items == 0) return MFS_OK;
     KernelArgs a;
-    a.items = pp.d_items.as<P2PItem>();
+    a.items = pp.items;
     a.centre = L.centre;
     a.trg_body = L.trg_body;
     a.src_ptr = L.src_ptr;
@@ -485,12 +497,12 @@ int launch_p2p(const P2PPlan &pp, const P2PLaunch &L, hipStream_t s) {
     a.addend = direct ? L.addend : nullptr;
     a.accumulate = direct ? (L.accumulate ? 1 : 0) : 0;
     a.out_stride = L.n_val;
-    a.n_items = (int)pp.items.size();
+    a.n_items = pp.n_items;
     a.queue = nullptr;
-    dim3 grid((unsigned)pp.items.size());
+    dim3 grid((unsigned)pp.n_items);
     if (pp.persistent) {
-        a.queue = pp.d_counter.as<int>();
-        grid = dim3((unsigned)std::min<size_t>(pp.items.size(), (size_t)pp.persistent_grid));
+        a.queue = pp.counter;
+        grid = dim3((unsigned)std::min(pp.n_items, pp.persistent_grid));
         reset_counter_kernel<<<1, 1, 0, s>>>(a.queue);
         MFS_HIP_TRY(hipGetLastError());
     }

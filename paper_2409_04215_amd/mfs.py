@@ -84,6 +84,7 @@ def lib():
         L.mfs_plan_last_solve.argtypes = [_vp, _i32p, _i32p]
         L.mfs_plan_set_launch.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]
         L.mfs_plan_set_progress.argtypes = [_vp, _PROGRESS_FN, _vp]
+        L.mfs_plan_set_stop_factor.argtypes = [_vp, ctypes.c_double]
         # (n_sys, structure, trg_xyz, src_xyz | trg_normal) + remaining pointers, flags, prec, stream
         L.mfs_p2p_stokes_pressure.argtypes = geo + [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_p2p_stokes_traction.argtypes = geo + [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
@@ -415,6 +416,10 @@ class Plan:
 
         self._progress_cb = _PROGRESS_FN(tramp)  # kept alive while set
         _check(lib().mfs_plan_set_progress(self._h, self._progress_cb, None), "mfs_plan_set_progress")
+
+    def set_stop_factor(self, factor: float):
+        """GMRES iterates to factor * tol (see mfs_plan_set_stop_factor; default 0.1)."""
+        _check(lib().mfs_plan_set_stop_factor(self._h, float(factor)), "mfs_plan_set_stop_factor")
 
     def set_graph(self, enable: bool = True):
         """Replay the GMRES matvec from a captured hipGraph (see mfs.h)."""
