@@ -108,6 +108,26 @@ int mfs_p2p_stokes(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *bo
                    const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
                    const double *src_f, double *out_u, double mu, int flags, int prec, void *stream);
 
+/* mfs_p2p_stokes for callers that cannot allocate device memory (code that may
+ * not call hipMalloc or hipFree: tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, arithmetic, launch shape and results as
+ * mfs_p2p_stokes (bit for bit), but every device buffer beyond the inputs and
+ * the output lives in one library-owned scratch array of 64 MiB per GPU that
+ * the library holds from load until the process ends; the call allocates
+ * nothing and keeps nothing between calls.  Limits: at most 65536 bodies,
+ * 32768 work items (about 2e6 targets) and 64 MiB of scratch: 36 B per
+ * source and 20 B per target (mixed) or 68 B and 36 B (FP64), plus 24 B per
+ * target and split slice when the sources are split; beyond them it returns
+ * MFS_EINVAL before any launch.  The kernels write every scratch
+ * value they read, so nothing needs clearing between calls.  Every call on a
+ * GPU shares that GPU's scratch: calls are serialised on the host (a mutex)
+ * and each waits for its stream before it returns (synchronous), so calls
+ * that overlap on one GPU from other processes or through other library
+ * copies race. */
+int mfs_p2p_stokes_noalloc(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                           const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                           const double *src_f, double *out_u, double mu, int flags, int prec, void *stream);
+
 /* Backward of the pairing  Phi = sum_i w_i . out_i  for the sums above
  * (flags as there; ACCUMULATE adds into every gradient that is requested):
  *   grad_src  [n_src] / [n_src][3]  dPhi/ds_j   = sum_i G(y_j - x_i) w_i

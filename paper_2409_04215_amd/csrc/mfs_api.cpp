@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "mfs_internal.h"
@@ -960,6 +961,144 @@ static int upload_geometry(mfs_plan_s *p, const double *centre, const double *ro
     return MFS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free Stokes pair sum (mfs_p2p_stokes_noalloc).  Its device
+// scratch is one file-scope array: every GPU the library runs on holds a copy of
+// kScratchBytes from module load until the process ends.  In host code the name
+// `scratch` is only a host-side stand-in; its device address on the current
+// device comes from hipGetSymbolAddress (taken once per device, on the first
+// call there) and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int64_t kNoAllocMaxBodies = int64_t(1) << 16;
+constexpr int64_t kNoAllocMaxItems = int64_t(1) << 15;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Host staging of the structure and work items: static storage (no heap), used
+// under g_noalloc_mutex by one call at a time.
+struct NoAllocHost {
+    int32_t trg32[kNoAllocMaxBodies + 1], src32[kNoAllocMaxBodies + 1];
+    P2PItem items[kNoAllocMaxItems], sorted[kNoAllocMaxItems];
+    double work[kNoAllocMaxItems];
+    int32_t order[kNoAllocMaxItems];
+};
+NoAllocHost g_noalloc_host;
+std::mutex g_noalloc_mutex;
+void *g_scratch_ptr[kNoAllocMaxDevices];  // device address of `scratch` per device (guarded by the mutex)
+
+int scratch_address(void **out) {
+    int dev = 0;
+    MFS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(MFS_EUNSUPPORTED, "device index beyond 63");
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MFS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MFS_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int p2p_stokes_noalloc(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                       const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz, const double *str,
+                       double *out, double mu, int flags, int prec, void *stream) {
+    int64_t nb, nt, ns;
+    MFS_TRY(check_structure(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, &nb, &nt, &ns));
+    MFS_TRY(check_prec(prec));
+    if (flags & ~(MFS_SKIP_SAME_BODY | MFS_ACCUMULATE)) return fail(MFS_EINVAL, "unknown flags");
+    if (!finite_pos(mu)) return fail(MFS_EINVAL, "mu must be finite and > 0");
+    if ((nt > 0 && (!trg_xyz || !out)) || (ns > 0 && (!src_xyz || !str)))
+        return fail(MFS_EINVAL, "NULL data pointer");
+    if (nb > kNoAllocMaxBodies)
+        return fail(MFS_EINVAL, "mfs_p2p_stokes_noalloc takes at most " + std::to_string(kNoAllocMaxBodies) + " bodies");
+    if (nt == 0) return MFS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    NoAllocHost &h = g_noalloc_host;
+    int64_t n_items = 0;
+    int n_split = 1;
+    MFS_TRY(generate_p2p_items(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, nullptr, 3, nullptr, MFS_STOKES, mu, 1,
+                               2048, h.items, h.work, h.order, h.sorted, kNoAllocMaxItems, &n_items, &n_split));
+    // scratch layout (256-byte aligned pieces)
+    const bool f32 = prec == MFS_MIXED;
+    const size_t sz_ptr = align256((nb + 1) * sizeof(int32_t));
+    const size_t sz_tb = align256(nt * sizeof(int32_t)), sz_sb = align256(ns * sizeof(int32_t));
+    const size_t sz_c = align256(nb * 3 * sizeof(double));
+    const size_t sz_to = align256(nt * (f32 ? 16 : 32));
+    const size_t sz_so = align256(ns * (f32 ? sizeof(SrcS32) : sizeof(SrcS64)));
+    const size_t sz_it = align256(n_items * sizeof(P2PItem));
+    const size_t sz_pa = n_split > 1 ? align256((size_t)n_split * 3 * nt * sizeof(double)) : 0;
+    const size_t need = 2 * sz_ptr + sz_tb + sz_sb + sz_c + sz_to + sz_so + sz_it + sz_pa;
+    if (need > kScratchBytes)
+        return fail(MFS_EINVAL, "mfs_p2p_stokes_noalloc needs " + std::to_string(need) +
+                                    " bytes of scratch for these sizes; it holds " + std::to_string(kScratchBytes));
+    void *base = nullptr;
+    MFS_TRY(scratch_address(&base));
+    unsigned char *q = static_cast<unsigned char *>(base);
+    int32_t *d_trg_ptr = reinterpret_cast<int32_t *>(q);
+    q += sz_ptr;
+    int32_t *d_src_ptr = reinterpret_cast<int32_t *>(q);
+    q += sz_ptr;
+    int32_t *d_trg_body = reinterpret_cast<int32_t *>(q);
+    q += sz_tb;
+    int32_t *d_src_body = reinterpret_cast<int32_t *>(q);
+    q += sz_sb;
+    double *d_centre = reinterpret_cast<double *>(q);
+    q += sz_c;
+    void *d_trg_off = q;
+    q += sz_to;
+    void *d_src_ops = q;
+    q += sz_so;
+    P2PItem *d_items = reinterpret_cast<P2PItem *>(q);
+    q += sz_it;
+    double *d_partial = sz_pa ? reinterpret_cast<double *>(q) : nullptr;
+    for (int64_t b = 0; b <= nb; ++b) {
+        h.trg32[b] = (int32_t)body_trg_ptr[b];
+        h.src32[b] = (int32_t)body_src_ptr[b];
+    }
+    MFS_HIP_TRY(hipMemcpyAsync(d_trg_ptr, h.trg32, (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFS_HIP_TRY(hipMemcpyAsync(d_src_ptr, h.src32, (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (n_items) MFS_HIP_TRY(hipMemcpyAsync(d_items, h.sorted, n_items * sizeof(P2PItem), hipMemcpyHostToDevice, s));
+    MFS_TRY(launch_fill_body_ids(nb, d_trg_ptr, d_trg_body, s));
+    MFS_TRY(launch_fill_body_ids(nb, d_src_ptr, d_src_body, s));
+    MFS_TRY(launch_body_refpoint(nb, d_src_ptr, d_trg_ptr, src_xyz, trg_xyz, d_centre, s));
+    MFS_TRY(launch_make_trg_off(nt, trg_xyz, d_trg_body, d_centre, prec, d_trg_off, s));
+    MFS_TRY(launch_make_src(ns, MFS_STOKES, src_xyz, d_src_body, d_centre, str, prec, d_src_ops, s));
+    P2PItems it;
+    it.items = d_items;
+    it.n_items = (int)n_items;
+    it.n_split = n_split;
+    it.tpl = 1;
+    P2PLaunch L;
+    L.prec = prec;
+    L.skip_same = (flags & MFS_SKIP_SAME_BODY) != 0;
+    L.accumulate = (flags & MFS_ACCUMULATE) != 0;
+    L.centre = d_centre;
+    L.trg_body = d_trg_body;
+    L.src_ptr = d_src_ptr;
+    L.trg_off = d_trg_off;
+    L.srcS = d_src_ops;
+    L.out = out;
+    L.partial = d_partial;
+    L.n_val = 3 * nt;
+    MFS_TRY(launch_p2p(it, L, s));
+    // the staging above and the scratch are reused by the next call
+    MFS_HIP_TRY(hipStreamSynchronize(s));
+    return MFS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *mfs_last_error(void) { return g_last_error.c_str(); }
@@ -977,6 +1116,13 @@ int mfs_p2p_stokes(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *bo
                    double *out_u, double mu, int flags, int prec, void *stream) {
     return p2p_standalone(MFS_STOKES, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f, out_u,
                           mu, flags, prec, stream);
+}
+
+int mfs_p2p_stokes_noalloc(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,
+                           const int64_t *body_src_ptr, const double *trg_xyz, const double *src_xyz,
+                           const double *src_f, double *out_u, double mu, int flags, int prec, void *stream) {
+    return p2p_stokes_noalloc(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f, out_u, mu,
+                              flags, prec, stream);
 }
 
 int mfs_p2p_laplace_backward(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t *body_trg_ptr,

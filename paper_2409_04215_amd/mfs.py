@@ -64,6 +64,7 @@ def lib():
         geo = [ctypes.c_int64, _i64p, _i64p, _i64p, _vp, _vp]
         L.mfs_p2p_laplace.argtypes = geo + [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_p2p_stokes.argtypes = geo + [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp]
+        L.mfs_p2p_stokes_noalloc.argtypes = geo + [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_p2p_laplace_backward.argtypes = geo + [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
         L.mfs_p2p_stokes_backward.argtypes = geo + [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int,
                                                     ctypes.c_int, _vp]
@@ -161,6 +162,18 @@ def p2p_stokes(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f
         out = torch.zeros(trg_xyz.shape[0], 3, dtype=torch.float64, device=trg_xyz.device)
     _check(lib().mfs_p2p_stokes(*keep[3], _ptr(trg_xyz), _ptr(src_xyz), _ptr(src_f), _ptr(out), float(mu), flags,
                                 prec, _stream(stream)), "mfs_p2p_stokes")
+    return out
+
+
+def p2p_stokes_noalloc(sys_body_ptr, body_trg_ptr, body_src_ptr, trg_xyz, src_xyz, src_f, mu=1.0,
+                       flags=SKIP_SAME_BODY, prec=MIXED, out=None, stream=None) -> torch.Tensor:
+    """p2p_stokes through mfs_p2p_stokes_noalloc: no device allocation inside the
+    library (its scratch is a fixed per-GPU array; synchronous; see mfs.h)."""
+    keep = _geo(sys_body_ptr, body_trg_ptr, body_src_ptr)
+    if out is None:
+        out = torch.zeros(trg_xyz.shape[0], 3, dtype=torch.float64, device=trg_xyz.device)
+    _check(lib().mfs_p2p_stokes_noalloc(*keep[3], _ptr(trg_xyz), _ptr(src_xyz), _ptr(src_f), _ptr(out), float(mu),
+                                        flags, prec, _stream(stream)), "mfs_p2p_stokes_noalloc")
     return out
 
 
