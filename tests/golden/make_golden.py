@@ -4,6 +4,8 @@ this script.  Calls only oracle/ and the seeded input generators.
     python tests/golden/make_golden.py            # ellipsoids_100 mobility / elastance (minutes)
     python tests/golden/make_golden.py two_way    # ellipsoids_100 resistance -> mobility (2-way error)
     python tests/golden/make_golden.py rows_10000 # 10^4 Type T case: 1000 sampled rows (tens of minutes)
+    python tests/golden/make_golden.py rows_10000_model  # the float32 model on 100 of those rows
+    python tests/golden/make_golden.py rows_1000  # ellipsoids_1000: 2000 sampled rows, oracle and float32 model
     python tests/golden/make_golden.py batched    # batched_64: a stated subset of the 64 systems (~1.5 h)
     python tests/golden/make_golden.py e1000_laplace | e1000_stokes   # ellipsoids_1000 (~1 h / ~4 h)
 
@@ -21,6 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import mfs_workloads as W  # noqa: E402
+from oracle import fp32_model as M  # noqa: E402
 from oracle import mfs_oracle as O  # noqa: E402
 
 TOL = 1e-10
@@ -173,7 +176,54 @@ def rows_10000():
     _log("10^4 rows stored")
 
 
-JOBS = {"two_way": two_way, "rows_10000": rows_10000, "batched": batched,
+def rows_1000():
+    """ellipsoids_1000, both kinds: the right-hand side and the matvecs of a
+    seeded random vector and of a seeded smooth field on 2000 sampled
+    collocation rows, by the FP64 oracle and by its float32 model
+    (oracle/fp32_model.py, which sizes the mixed bars)."""
+    for kind, name in ((W.STOKES, "stokes"), (W.LAPLACE, "laplace")):
+        t0 = time.time()
+        wl = W.ellipsoids_1000(kind)
+        pr = O.Problem.from_workload(wl)
+        rows = np.sort(np.random.default_rng(81).choice(pr.X.shape[0], 2000, replace=False))
+        g = W.random_vector(pr.n_gamma, 82)
+        sm = W.smooth_vector(wl, 83)
+        cols = [pr.rhs(wl.net[0], rows=rows)[0], pr.matvec(g, rows=rows), pr.matvec(sm, rows=rows)]
+        _log(f"ellipsoids_1000 {name}: oracle rows, {time.time() - t0:.0f} s")
+        cols += [M.rhs(pr, wl.net[0], rows=rows), M.matvec(pr, g, rows=rows), M.matvec(pr, sm, rows=rows)]
+        _log(f"ellipsoids_1000 {name}: float32 model rows, {time.time() - t0:.0f} s")
+        d = 3 if kind == W.STOKES else 1
+        tab = np.concatenate([rows[:, None].astype(np.float64)] + [c.reshape(-1, d) for c in cols], axis=1)
+        hdr = (f"the seeded ellipsoids_1000 workload ({name}): 2000 collocation rows drawn by default_rng(81);\n"
+               f"columns: row, then ({d} each) the right-hand side b, A g for g = random_vector(n_gamma, 82), "
+               f"A s for s = smooth_vector(83) by the FP64 oracle, then the same three by its float32 model.\n"
+               f"{time.time() - t0:.0f} s.  Written by tests/golden/make_golden.py rows_1000 (oracle/ only).")
+        np.savetxt(os.path.join(HERE, f"ellipsoids_1000_{name}_rows.txt"), tab, fmt="%.17e", header=hdr)
+
+
+def rows_10000_model():
+    """The float32 model of the 10^4 case's stored rows, on the first 100 of them."""
+    t0 = time.time()
+    tab = np.loadtxt(os.path.join(HERE, "ellipsoids_10000_rows.txt"))[:100]
+    rows = tab[:, 0].astype(np.int64)
+    wl = W.ellipsoids_10000(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    g = W.random_vector(pr.n_gamma, 87)
+    sm = W.smooth_vector(wl, 88)
+    cols = [M.rhs(pr, wl.net[0], rows=rows)]
+    _log(f"10^4 model: right-hand side rows, {time.time() - t0:.0f} s")
+    cols.append(M.matvec(pr, g, rows=rows))
+    _log(f"10^4 model: matvec rows (random), {time.time() - t0:.0f} s")
+    cols.append(M.matvec(pr, sm, rows=rows))
+    out = np.concatenate([rows[:, None].astype(np.float64)] + [c.reshape(-1, 3) for c in cols], axis=1)
+    hdr = ("the float32 model (oracle/fp32_model.py) of the first 100 stored rows of ellipsoids_10000_rows.txt;\n"
+           "columns: row, right-hand side b (3), A g (3), A s (3) (the same vectors).\n"
+           f"{time.time() - t0:.0f} s.  Written by tests/golden/make_golden.py rows_10000_model (oracle/ only).")
+    np.savetxt(os.path.join(HERE, "ellipsoids_10000_model_rows.txt"), out, fmt="%.17e", header=hdr)
+    _log("10^4 model rows stored")
+
+
+JOBS = {"rows_1000": rows_1000, "rows_10000_model": rows_10000_model, "two_way": two_way, "rows_10000": rows_10000, "batched": batched,
         "e1000_laplace": lambda: e1000(W.LAPLACE), "e1000_stokes": lambda: e1000(W.STOKES)}
 
 

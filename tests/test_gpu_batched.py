@@ -3,8 +3,15 @@ Stokes mixed, in one plan (one pair-sum launch and one grouped GEMM per step
 for the whole batch, per-system GMRES).  Each system is compared with the
 oracle solving it alone.
 
-Tolerances as in test_gpu_operator: FP64 matvec 1e-10, mixed matvec 1e-4,
-FP64 solves (tol 1e-10) 1e-8, mixed solves at tol 1e-5 within 1e-5.
+Tolerances (rel_inf per system): FP64 matvec 1e-10, FP64 solves (tol 1e-10)
+1e-8.  Mixed matvec: 4 x the error of the float32 model of the same system's
+matvec (oracle/fp32_model.py).  Mixed solves at tol t: 4 x the larger of
+the stopping-residual limit and the float32-operator limit of
+oracle/fp32_model.py solve_bars, at most 1e-5 (the target for the reported
+outputs).  The full 64-suspension workload
+is compared with the oracle's stored solutions of a subset of its systems
+(tests/golden/batched_64_subset.txt): FP64 within 1e-8 and mixed at the
+benchmark tolerance 1e-5 within 1e-5, every stored system.
 """
 import numpy as np
 import pytest
@@ -12,6 +19,7 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
@@ -59,28 +67,33 @@ def test_batched_matvec_matches_per_system_oracle():
     g = W.random_vector(plan.n_gamma, 51)
     ref = np.concatenate([pr.matvec(g[sl[s][0]]) for s, pr in enumerate(probs)])
     ref_t = np.concatenate([pr.matvec_T(g[sl[s][0]]) for s, pr in enumerate(probs)])
-    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-4)):
+    bars = [M.bar(max(rel_inf(M.matvec(pr, g[sl[s][0]]), ref[sl[s][0]]),
+                      rel_inf(M.matvec_T(pr, g[sl[s][0]]), ref_t[sl[s][0]]))) for s, pr in enumerate(probs)]
+    for prec in (mfs.FP64, mfs.MIXED):
         got = plan.matvec(_dev(g), prec).cpu().numpy()
         got_t = plan.matvec_adjoint(_dev(g), prec).cpu().numpy()
         for s in range(wl.n_sys):
             e = (rel_inf(got[sl[s][0]], ref[sl[s][0]]), rel_inf(got_t[sl[s][0]], ref_t[sl[s][0]]))
-            assert max(e) <= tol, (prec, s, e)
+            assert max(e) <= (1e-10 if prec == mfs.FP64 else bars[s]), (prec, s, e, bars[s])
 
 
 def test_batched_solve_matches_per_system_oracle():
     mfs = _mfs()
     wl, probs = _small_batch()
     sl = _sys_slices(wl)
-    ref = [pr.solve(wl.net[s], tol=1e-12)["out"].reshape(-1) for s, pr in enumerate(probs)]
-    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-5, 1e-5)):
+    sols = [pr.solve(wl.net[s], tol=1e-12) for s, pr in enumerate(probs)]
+    ref = [sol["out"].reshape(-1) for sol in sols]
+    mixed_bars = [M.solve_bars(pr, wl.net[s], 1e-5, sols[s], cap=1e-5)["out"] for s, pr in enumerate(probs)]
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-5)):
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
         assert info["status"] == mfs.MFS_OK
         assert np.all(info["relres"] <= tol)
         got = out.cpu().numpy()
         errs = [rel_inf(got[sl[s][1]], ref[s]) for s in range(wl.n_sys)]
-        print(prec, "iters", info["iters"], "errs", np.max(errs))
-        assert max(errs) <= bar
+        bars = [1e-8] * wl.n_sys if prec == mfs.FP64 else mixed_bars
+        print(prec, "iters", info["iters"], "errs", np.max(errs), "worst err / bar", max(e / b for e, b in zip(errs, bars)))
+        assert all(e <= b for e, b in zip(errs, bars))
 
 
 def test_distinct_shape_per_body():
@@ -97,34 +110,44 @@ def test_distinct_shape_per_body():
     wl = W.Workload("distinct", shapes, cen, rot, np.arange(P, dtype=np.int32), np.array([0, P]),
                     np.array([W.STOKES], np.int32), [F])
     pr = O.Problem.from_workload(wl)
-    ref = pr.solve(F, tol=1e-12)["out"]
+    sol = pr.solve(F, tol=1e-12)
     g = W.random_vector(pr.n_gamma, 62)
     plan = mfs.Plan.from_workload(wl, mfs.MIXED)
     assert rel_inf(plan.matvec(_dev(g), mfs.FP64).cpu().numpy(), pr.matvec(g)) <= 1e-10
     out, info = plan.solve(_dev(F), tol=1e-8)
-    assert rel_inf(out.cpu().numpy(), ref) <= 1e-6
+    assert rel_inf(out.cpu().numpy(), sol["out"]) <= M.solve_bars(pr, F, 1e-8, sol, cap=1e-5)["out"]
 
 
 @pytest.mark.timeout(900)
 def test_batched_64_full():
     """The full 64-suspension workload (6917 bodies, 32 Stokes + 32 Laplace,
-    one shape per suspension): mixed batched solve, every system converged
-    in FP64 terms, and the smallest systems of each kind against the oracle."""
+    one shape per suspension), the benchmark's default: every system converged
+    in FP64 terms, and the stored oracle solutions of a subset of its systems
+    (every system of at most 150 bodies and the largest of each kind, solved
+    alone by the FP64 oracle at GMRES tol 1e-10) matched by the FP64 batched
+    solve at tol 1e-10 (1e-8) and by the mixed one at the benchmark tolerance
+    1e-5 (1e-5), system by system."""
+    import os
     mfs = _mfs()
     wl = W.batched_64()
-    plan = mfs.Plan.from_workload(wl, mfs.MIXED)
-    out, info = plan.solve(_dev(net_flat(wl)), tol=1e-5)
-    print("iters per system", info["iters"], "max relres", info["relres"].max())
-    assert info["status"] == mfs.MFS_OK and np.all(info["relres"] <= 1e-5)
-    sl = _sys_slices(wl)
-    got = out.cpu().numpy()
+    tab = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_64_subset.txt"),
+                     ndmin=2)
+    stored = sorted(set(tab[:, 0].astype(int)))
     sizes = np.diff(wl.sys_body_ptr)
-    picks = []
-    for kind in (W.STOKES, W.LAPLACE):
-        idx = [s for s in range(wl.n_sys) if wl.sys_kind[s] == kind]
-        picks += sorted(idx, key=lambda s: sizes[s])[:2]
-    for s in picks:
-        ref = O.Problem.from_workload(wl, s).solve(wl.net[s], tol=1e-10)["out"].reshape(-1)
-        e = rel_inf(got[sl[s][1]], ref)
-        print("system", s, "bodies", sizes[s], "kind", wl.sys_kind[s], "err", e)
-        assert e <= 1e-5
+    assert max(sizes[stored]) == 473 and 438 in sizes[stored], "stored subset incomplete"
+    sl = _sys_slices(wl)
+    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-5, 1e-5)):
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
+        print(prec, "iters per system", info["iters"], "max relres", info["relres"].max(), flush=True)
+        assert info["status"] == mfs.MFS_OK and np.all(info["relres"] <= tol)
+        got = out.cpu().numpy()
+        worst = (0.0, -1)
+        for s in stored:
+            rows = tab[tab[:, 0] == s]
+            ref = (rows[:, 2:8] if wl.sys_kind[s] == W.STOKES else rows[:, 2]).reshape(-1)
+            worst = max(worst, (rel_inf(got[sl[s][1]], ref), s))
+        print(f"prec={prec} tol={tol:g}: {len(stored)} stored systems, worst rel_inf {worst[0]:.2e} "
+              f"(system {worst[1]}, {sizes[worst[1]]} bodies)", flush=True)
+        assert worst[0] <= bar
+        plan.close()

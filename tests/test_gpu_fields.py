@@ -3,11 +3,12 @@ residual (eq. (residual)) on the GPU against the oracle's plain loops.
 
 Tolerances (rel_inf = max|x - ref| / max|ref|):
 * FP64: 1e-12 (pressure, gradient), 1e-11 (traction: three more products).
-* Mixed: FP32 pairs with FP64 accumulation per run of <= 64 sources, as for
-  the pair sums (2e-5); traction 5e-5 (r^-5 and two dot products per pair).
+* Mixed: 4 x the error of the float32 model of the same field on the same
+  input (oracle/fp32_model.py: FP32 offsets, strengths and pair terms, runs
+  of 64 sources in float32, added in float64).
 * Surface residual: the GPU evaluates eps from the oracle's own strengths and
-  rigid motions; |eps_gpu - eps_ref| <= 1e-10 (FP64) and 2e-6 (mixed: the
-  FP32 pair sums err by ~1e-7 of |u|, and |u| ~ |g| on the surface).
+  rigid motions; |eps_gpu - eps_ref| <= 1e-10 (FP64) and, mixed, 4 x the
+  largest difference of the float32 model's eps.
 """
 import numpy as np
 import pytest
@@ -15,6 +16,7 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf, structure
 
 pytestmark = pytest.mark.gpu
@@ -50,7 +52,11 @@ def test_field_sums_match_oracle(skip):
     ref_t = O.p2p_field(O.FIELD_TRACTION, X, tb, Y, sb, f, normal=n, skip_same_body=skip)
     ref_g = O.p2p_field(O.FIELD_LAPLACE_GRADIENT, X, tb, Y, sb, q, skip_same_body=skip)
     flags = mfs.SKIP_SAME_BODY if skip else 0
-    for prec, tp_, tt_, tg_ in ((mfs.FP64, 1e-12, 1e-11, 1e-12), (mfs.MIXED, 2e-5, 5e-5, 2e-5)):
+    first = M.ref_first_source(wl.n_body, sb, Y, tb, X)
+    mixed = (M.bar(rel_inf(M.field(M.FIELD_PRESSURE, X, tb, Y, sb, f, first, skip=skip), ref_p)),
+             M.bar(rel_inf(M.field(M.FIELD_TRACTION, X, tb, Y, sb, f, first, normal=n, skip=skip), ref_t)),
+             M.bar(rel_inf(M.field(M.FIELD_LAPLACE_GRADIENT, X, tb, Y, sb, q, first, skip=skip), ref_g)))
+    for prec, tp_, tt_, tg_ in ((mfs.FP64, 1e-12, 1e-11, 1e-12), (mfs.MIXED, *mixed)):
         p = mfs.p2p_stokes_pressure(sp, tp, pp, _dev(X), _dev(Y), _dev(f), flags, prec)
         t = mfs.p2p_stokes_traction(sp, tp, pp, _dev(X), _dev(n), _dev(Y), _dev(f), flags, prec)
         g = mfs.p2p_laplace_gradient(sp, tp, pp, _dev(X), _dev(Y), _dev(q), flags, prec)
@@ -79,7 +85,10 @@ def test_fields_two_systems_do_not_interact():
     pp = np.concatenate([[0], np.cumsum([37] * 3 + [50] * 4)]).astype(np.int64)
     ref = np.concatenate([O.p2p_field(O.FIELD_PRESSURE, Xa, tba, Ya, sba, f[:len(Ya)]),
                           O.p2p_field(O.FIELD_PRESSURE, Xb, tbb, Yb, sbb, f[len(Ya):])])
-    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 2e-5)):
+    model = np.concatenate([
+        M.field(M.FIELD_PRESSURE, Xa, tba, Ya, sba, f[:len(Ya)], M.ref_first_source(3, sba, Ya, tba, Xa)),
+        M.field(M.FIELD_PRESSURE, Xb, tbb, Yb, sbb, f[len(Ya):], M.ref_first_source(4, sbb, Yb, tbb, Xb))])
+    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, M.bar(rel_inf(model, ref)))):
         p = mfs.p2p_stokes_pressure(sp, tp, pp, _dev(X), _dev(Y), _dev(f), 0, prec)
         assert rel_inf(p.cpu().numpy(), ref) <= tol
 
@@ -112,7 +121,8 @@ def test_surface_residual_matches_oracle(kind):
     sol = pr.solve(wl.net[0], tol=1e-12)
     test = W.fibonacci_sphere(500, 1.0)
     ref = pr.surface_residual(sol["sigma"], sol["out"], test)
-    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 2e-6)):
+    bar = M.bar(np.abs(M.surface_residual(pr, sol["sigma"], sol["out"], test) - ref).max())
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, bar)):
         plan = mfs.Plan.from_workload(wl, prec)
         eps = plan.surface_residual(_dev(sol["sigma"]), _dev(np.asarray(sol["out"]).reshape(-1)), test, prec=prec)
         e = np.abs(eps.cpu().numpy() - ref).max()

@@ -13,6 +13,7 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
@@ -68,11 +69,12 @@ def test_autotune_keeps_results(kind):
     tpl, mi, ms = plan.autotune(mfs.MIXED, reps=2)
     assert abs(tpl) in (1, 2) and mi in (1024, 2048, 4096, 8192, 16384) and ms > 0
     assert rel_inf(plan.matvec(_dev(g), mfs.FP64).cpu().numpy(), ref) <= 1e-10
-    assert rel_inf(plan.matvec(_dev(g), mfs.MIXED).cpu().numpy(), ref) <= 1e-4
+    assert rel_inf(plan.matvec(_dev(g), mfs.MIXED).cpu().numpy(), ref) <= M.bar(rel_inf(M.matvec(pr, g), ref))
     assert rel_inf(plan.matvec_adjoint(_dev(g), mfs.FP64).cpu().numpy(), pr.matvec_T(g)) <= 1e-10
     out, info = plan.solve(_dev(net_flat(wl)), tol=1e-8)
     assert info["status"] == mfs.MFS_OK
-    assert rel_inf(out.cpu().numpy(), pr.solve(wl.net[0], tol=1e-12)["out"]) <= 1e-6
+    sol = pr.solve(wl.net[0], tol=1e-12)
+    assert rel_inf(out.cpu().numpy(), sol["out"]) <= M.solve_bars(pr, wl.net[0], 1e-8, sol, cap=1e-5)["out"]
 
 
 @pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
@@ -84,12 +86,13 @@ def test_every_launch_shape(kind):
     pr = O.Problem.from_workload(wl)
     g = W.random_vector(pr.n_gamma, 76)
     ref, ref_t = pr.matvec(g), pr.matvec_T(g)
+    bar = M.bar(max(rel_inf(M.matvec(pr, g), ref), rel_inf(M.matvec_T(pr, g), ref_t)))
     plan = mfs.Plan.from_workload(wl, mfs.MIXED)
     for tpl in (1, 2):
         for items in (1, 64, 16384):
             for per in (False, True):
                 plan.set_launch(tpl, items, per)
-                for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-4)):
+                for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, bar)):
                     e = (rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref),
                          rel_inf(plan.matvec_adjoint(_dev(g), prec).cpu().numpy(), ref_t))
                     assert max(e) <= tol, (tpl, items, per, prec, e)

@@ -18,6 +18,7 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
@@ -48,8 +49,10 @@ def test_moved_plan_equals_new_plan(kind):
     pr_b = O.Problem.from_workload(b)
     g = W.random_vector(pr_b.n_gamma, 142)
     ref_mv = pr_b.matvec(g)
-    ref_out = pr_b.solve(b.net[0], tol=1e-12)["out"]
-    for prec, tol_mv, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-4, 1e-6)):
+    sol_b = pr_b.solve(b.net[0], tol=1e-12)
+    ref_out = sol_b["out"]
+    mixed = (M.bar(rel_inf(M.matvec(pr_b, g), ref_mv)), M.solve_bars(pr_b, b.net[0], 1e-10, sol_b, cap=1e-5)["out"])
+    for prec, tol_mv, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, *mixed)):
         moved = mfs.Plan.from_workload(a, prec)
         moved.solve(_dev(net_flat(a)), tol=1e-8)  # used at the old positions first
         moved.set_bodies(b.centre, b.rot)
@@ -77,7 +80,10 @@ def test_moved_plan_graph_replay_and_bodies_of_several_shapes():
     for wl in (a, b):
         wl.shapes = shapes
         wl.shape_of_body = np.array([0, 1, 2, 1, 0, 2], np.int32)
-    ref = O.Problem.from_workload(b).solve(b.net[0], tol=1e-12)["out"]
+    pr_b = O.Problem.from_workload(b)
+    sol_b = pr_b.solve(b.net[0], tol=1e-12)
+    ref = sol_b["out"]
+    bar = M.solve_bars(pr_b, b.net[0], 1e-8, sol_b, cap=1e-5)["out"]
     moved = mfs.Plan.from_workload(a, mfs.MIXED)
     moved.set_graph(True)
     moved.solve(_dev(net_flat(a)), tol=1e-8)  # captures the matvec graph at the old positions
@@ -89,7 +95,7 @@ def test_moved_plan_graph_replay_and_bodies_of_several_shapes():
         out_f, _ = fresh.solve(_dev(net_flat(b)), tol=1e-8)
         assert info_m["status"] == mfs.MFS_OK
         assert torch.equal(out_m, out_f)
-        assert rel_inf(out_m.cpu().numpy(), ref) <= 1e-6
+        assert rel_inf(out_m.cpu().numpy(), ref) <= bar
     moved.close()
     fresh.close()
 

@@ -4,13 +4,17 @@ in seconds (several GEMM tiles and ragged tails: 3N = 135 rows, 3M = 903).
 
 Tolerances, rel_inf = max|x - ref| / max|ref|:
 * FP64 operator pieces: 1e-10 (the pseudo-inverse amplifies rounding by up
-  to cond(S_L) ~ 1e5 on these shapes, times u = 1.1e-16).
-* MIXED operator pieces: 1e-4 on the matvec (FP32 pseudo-inverse blocks:
-  u32 * cond(S_L) on the rough parts of a random input, which the smooth
-  far field of the other bodies then damps; measured ~1e-6-1e-5).
+  to cond(S_L) ~ 1e5 on these shapes, times u = 1.1e-16); right-hand side
+  1e-12; completion strengths 1e-13 (FP64 on both paths).
+* MIXED operator pieces: 4 x the error of their float32 model on the same
+  input (oracle/fp32_model.py).
 * Solves: oracle at tol 1e-12.  GPU FP64 at tol 1e-10 -> outputs within 1e-8.
-  GPU MIXED at tol 1e-7 with FP64 residual refinement -> within 1e-6; at the
-  benchmark tolerance 1e-5 -> within 1e-5 (the spec bar).
+  GPU MIXED at tol t (FP64 residual refinement): 4 x the larger of two
+  limits (oracle/fp32_model.py solve_bars): the residual the mixed solve may
+  end at times the oracle's ratio of output error to residual, and the
+  change of the outputs under the float32 operator's own error at the
+  solution; at most 1e-5 for U and phi (the target for the outputs the
+  method reports).
 """
 import numpy as np
 import pytest
@@ -18,6 +22,7 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
@@ -53,7 +58,7 @@ def test_rhs(kind):
     mfs = _mfs()
     wl, pr = _case(kind)
     b_ref, s0_ref = pr.rhs(wl.net[0])
-    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 2e-5)):
+    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, M.bar(rel_inf(M.rhs(pr, wl.net[0]), b_ref)))):
         plan = _plan(wl, prec)
         b, s0 = plan.rhs(_dev(net_flat(wl)))
         assert rel_inf(s0.cpu().numpy(), s0_ref) <= 1e-13
@@ -71,7 +76,10 @@ def test_precond_apply(kind):
     ref_pp = pr.precondition(g)
     ref_t = np.concatenate([pr.pinv_apply_T(k, pr.sblock(v, k)) for k in range(wl.n_body)])
     ref_tp = np.concatenate([pr.pinv_apply_T(k, pr.project(k, pr.sblock(v, k))) for k in range(wl.n_body)])
-    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 5e-3)):
+    model = [M.precond_apply(pr, g), M.precond_apply(pr, g, project=True), M.precond_apply(pr, v, transpose=True),
+             M.precond_apply(pr, v, transpose=True, project=True)]
+    bar = M.bar(max(rel_inf(m, r) for m, r in zip(model, (ref_p, ref_pp, ref_t, ref_tp))))
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, bar)):
         got = plan.precond_apply(_dev(g), 0, prec).cpu().numpy()
         got_p = plan.precond_apply(_dev(g), mfs.PROJECT, prec).cpu().numpy()
         got_t = plan.precond_apply(_dev(v), mfs.TRANSPOSE, prec).cpu().numpy()
@@ -90,7 +98,8 @@ def test_matvec_and_adjoint(kind):
     w = W.random_vector(pr.n_gamma, 42)
     ref = pr.matvec(g)
     ref_t = pr.matvec_T(w)
-    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-4)):
+    bar = M.bar(max(rel_inf(M.matvec(pr, g), ref), rel_inf(M.matvec_T(pr, w), ref_t)))
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, bar)):
         got = plan.matvec(_dev(g), prec).cpu().numpy()
         got_t = plan.matvec_adjoint(_dev(w), prec).cpu().numpy()
         e = (rel_inf(got, ref), rel_inf(got_t, ref_t))
@@ -107,16 +116,21 @@ def test_solve(kind):
     mfs = _mfs()
     wl, pr = _case(kind)
     sol = pr.solve(wl.net[0], tol=1e-12)
-    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-7, 1e-6), (mfs.MIXED, 1e-5, 1e-5)):
+    bars = {tol: M.solve_bars(pr, wl.net[0], tol, sol, ("out", "sigma"), cap=1e-5) for tol in (1e-7, 1e-5)}
+    bars[1e-10] = {"out": 1e-8, "sigma": 1e-8}
+    for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, 1e-7), (mfs.MIXED, 1e-5)):
+        bar, bar_s = bars[tol]["out"], bars[tol]["sigma"]
         plan = _plan(wl, prec)
         out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
         assert info["status"] == mfs.MFS_OK
         got = out.cpu().numpy()
         e = rel_inf(got, sol["out"])
-        print(kind, prec, tol, "err", e, "iters", info["iters"], "relres", info["relres"], "oracle iters", sol["iters"])
-        assert e <= bar
         _, sigma = plan.extract(info["gamma"], info["s0"], want_sigma=True)
-        assert rel_inf(sigma.cpu().numpy(), sol["sigma"]) <= max(bar, 1e-8) * 100
+        es = rel_inf(sigma.cpu().numpy(), sol["sigma"])
+        print(kind, prec, tol, f"err {e:.2e} (bar {bar:.2e}) sigma {es:.2e} (bar {bar_s:.2e})", "iters", info["iters"],
+              "relres", info["relres"], "oracle iters", sol["iters"])
+        assert e <= bar
+        assert es <= bar_s
 
 
 def test_single_sphere_closed_forms():

@@ -6,22 +6,30 @@ Case: one cluster per kind of 6 prolate spheroids (1,1,2), N=45 proxies,
 M=301 collocation points per body (ragged 64-target blocks, several GEMM
 tiles); random unit-normal inputs for the operator pieces, N(0,1) net
 forces/torques or charges for the solves.  rel_inf = max|x - ref| / max|ref|
-over the stacked output.  Bars (the same as the per-entry-point tests):
+over the stacked output.
 
-  output                         FP64      MIXED
-  pair sum u (standalone)        1e-12     2e-5   FP32 pairs, runs of <=64 summed in FP32, FP64 accumulation
-  backward pair sums (ds, dx, dy) 1e-11    5e-5
-  completion strengths s0        1e-13     1e-13  FP64 on both paths
-  right-hand side b              1e-12     2e-5   one all-pairs sum
-  S_L^+ apply, (I-L) S_L^+ apply 1e-10     5e-3   FP32 factors: u32 * cond(S_L) on a random input
-  A gamma, A^T w                 1e-10     1e-4   the off-body sums damp the rough part again
-  gamma, lambda, sigma (solve)   1e-8      1e-3   FP64 solve at tol 1e-10; mixed at tol 1e-5
-  U or phi (solve)               1e-8      1e-5   the outputs the method reports
-  dJ/dc (adjoint)                1e-8      1e-5   J = sum |U|^2 or sum phi^2; FP64 tol 1e-12, mixed tol 1e-8
-  resistance / capacitance (Section 2): rhs 1e-13 / 1e-13, S^+ apply and
-  A gamma as above, F or q from the solve 1e-8 / 1e-5 (mixed solve at tol 1e-6)
+FP64 bars (fixed): pair sums 1e-12, backward pair sums 1e-11, completion and
+Dirichlet data 1e-13, right-hand side 1e-12, pseudo-inverse blocks and
+operators 1e-10 (two FP64 SVDs of S_L agree to about u64 cond(S_L)), solve
+outputs 1e-8 (FP64 GMRES at tol 1e-10 against the oracle at 1e-12).
 
-The oracle's solves run at tol 1e-12.
+Mixed bars, each derived on this input:
+* a step (pair sums, right-hand side, pseudo-inverse blocks, A gamma, A^T w):
+  4 x the error of the step's float32 model (oracle/fp32_model.py: the
+  oracle's formulas with the FP32 operands and arithmetic of the mixed path);
+* a solve output at GMRES tol t (gamma, lambda, sigma, U / phi, F / q): 4 x
+  the larger of two limits (oracle/fp32_model.py solve_bars): r x the ratio
+  of output error to relative residual of the oracle's own GMRES iterate at
+  r, where r = min(t, max(0.1 t, the float32 model's matvec error)) bounds
+  the residual the mixed solve ends at (the library iterates to 0.1 t and
+  refines until the FP64 residual is below t); and the change of the output
+  when the solution is moved by the float32 operator's own error at it.  At
+  most 1e-5 for U, phi, F, q (the target for the outputs the method reports);
+* the centre gradient: 4 x (the float32 model's error of the backward pair
+  sums on the oracle's adjoint solution and strengths + the oracle's error
+  at the adjoint's stopping residual), at most 1e-5.
+The completion strengths are FP64 on both paths (bar 1e-13).
+The oracle's reference solves run at tol 1e-12.
 """
 import os
 
@@ -31,31 +39,17 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf, structure
 
 pytestmark = pytest.mark.gpu
 
-BARS = {
-    "pair sum u": (1e-12, 2e-5),
-    "backward pair sums": (1e-11, 5e-5),
-    "completion s0": (1e-13, 1e-13),
-    "rhs b": (1e-12, 2e-5),
-    "S_L^+ apply": (1e-10, 5e-3),
-    "(I-L) S_L^+ apply": (1e-10, 5e-3),
-    "A gamma": (1e-10, 1e-4),
-    "A^T w": (1e-10, 1e-4),
-    "gamma": (1e-8, 1e-3),
-    "lambda": (1e-8, 1e-3),
-    "sigma": (1e-8, 1e-3),
-    "U / phi": (1e-8, 1e-5),
-    "dJ/dc": (1e-8, 1e-5),
-    "res: rhs b": (1e-13, 1e-13),
-    "res: S^+ apply": (1e-10, 5e-3),
-    "res: A gamma": (1e-10, 1e-4),
-    "res: F / q": (1e-8, 1e-5),
+FP64_BARS = {
+    "pair sum u": 1e-12, "backward pair sums": 1e-11, "completion s0": 1e-13, "rhs b": 1e-12,
+    "S_L^+ apply": 1e-10, "(I-L) S_L^+ apply": 1e-10, "A gamma": 1e-10, "A^T w": 1e-10,
+    "gamma": 1e-8, "lambda": 1e-8, "sigma": 1e-8, "U / phi": 1e-8, "dJ/dc": 1e-8,
+    "res: rhs b": 1e-13, "res: S^+ apply": 1e-10, "res: A gamma": 1e-10, "res: F / q": 1e-8,
 }
-
-
 def _mfs():
     from paper_2409_04215_amd import mfs
     return mfs
@@ -76,9 +70,10 @@ def _rows(kind):
     dim = 3 if kind == W.STOKES else 1
     rows = []
 
-    def add(name, prec, err):
+    def add(name, prec, err, mixed_bar=None):
+        bar = FP64_BARS[name] if prec == mfs.FP64 else mixed_bar
         rows.append((name, "stokes" if kind == W.STOKES else "laplace", "fp64" if prec == mfs.FP64 else "mixed",
-                     err, BARS[name][0 if prec == mfs.FP64 else 1]))
+                     err, bar))
 
     # standalone pair sums and their backward
     sp, tp, pp = structure(wl)
@@ -90,6 +85,12 @@ def _rows(kind):
     ref_u = O.p2p(kind, X, tb, Y, sb, s, 1.0, True)
     ref_gs = O.p2p(kind, Y, sb, X, tb, w, 1.0, True)
     ref_gx, ref_gy = O.p2p_grad(kind, X, tb, w, Y, sb, s, 1.0, True)
+    first = M.ref_first_source(wl.n_body, sb, Y, tb, X)
+    first_t = M.ref_first_source(wl.n_body, tb, X, sb, Y)
+    bar_u = M.bar(rel_inf(M.pair_sum(kind, X, tb, Y, sb, s, first), ref_u))
+    mgx, mgy = M.pair_grad(kind, X, tb, w, Y, sb, s, first)
+    bar_g = M.bar(max(rel_inf(M.pair_sum(kind, Y, sb, X, tb, w, first_t), ref_gs), rel_inf(mgx, ref_gx),
+                      rel_inf(mgy, ref_gy)))
     fwd = mfs.p2p_stokes if kind == W.STOKES else mfs.p2p_laplace
     bwd = mfs.p2p_stokes_backward if kind == W.STOKES else mfs.p2p_laplace_backward
     for prec in (mfs.FP64, mfs.MIXED):
@@ -98,12 +99,12 @@ def _rows(kind):
                     mfs.SKIP_SAME_BODY, prec)
         else:
             u = fwd(sp, tp, pp, _dev(X).view(-1, 3), _dev(Y).view(-1, 3), _dev(s), mfs.SKIP_SAME_BODY, prec)
-        add("pair sum u", prec, rel_inf(_np(u), ref_u))
+        add("pair sum u", prec, rel_inf(_np(u), ref_u), bar_u)
         gs, gx, gy = bwd(sp, tp, pp, _dev(X).view(-1, 3), _dev(Y).view(-1, 3),
                          _dev(s).view(-1, 3) if kind == W.STOKES else _dev(s),
                          _dev(w).view(-1, 3) if kind == W.STOKES else _dev(w), prec=prec)
         add("backward pair sums", prec, max(rel_inf(_np(gs), ref_gs), rel_inf(_np(gx), ref_gx),
-                                            rel_inf(_np(gy), ref_gy)))
+                                            rel_inf(_np(gy), ref_gy)), bar_g)
 
     # operator pieces
     net = _dev(net_flat(wl))
@@ -113,36 +114,54 @@ def _rows(kind):
     ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
     ref_pp = pr.precondition(g)
     ref_A, ref_AT = pr.matvec(g), pr.matvec_T(v)
+    mbar = {"rhs b": M.bar(rel_inf(M.rhs(pr, wl.net[0]), b_ref)),
+            "S_L^+ apply": M.bar(rel_inf(M.precondition(pr, g, project=False), ref_p)),
+            "(I-L) S_L^+ apply": M.bar(rel_inf(M.precondition(pr, g), ref_pp)),
+            "A gamma": M.bar(rel_inf(M.matvec(pr, g), ref_A)),
+            "A^T w": M.bar(rel_inf(M.matvec_T(pr, v), ref_AT)),
+            "completion s0": 1e-13}
     sol = pr.solve(wl.net[0], tol=1e-12)
+    tb_ = M.solve_bars(pr, wl.net[0], 1e-5, sol, ("gamma", "lam", "sigma"))
+    tb_.update(M.solve_bars(pr, wl.net[0], 1e-5, sol, ("out",), cap=1e-5))
     for prec in (mfs.FP64, mfs.MIXED):
         plan = mfs.Plan.from_workload(wl, prec)
         b, s0 = plan.rhs(net, prec=prec)
-        add("completion s0", prec, rel_inf(_np(s0), s0_ref))
-        add("rhs b", prec, rel_inf(_np(b), b_ref))
-        add("S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), ref_p))
-        add("(I-L) S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), mfs.PROJECT, prec)), ref_pp))
-        add("A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), ref_A))
-        add("A^T w", prec, rel_inf(_np(plan.matvec_adjoint(_dev(v), prec)), ref_AT))
+        add("completion s0", prec, rel_inf(_np(s0), s0_ref), mbar["completion s0"])
+        add("rhs b", prec, rel_inf(_np(b), b_ref), mbar["rhs b"])
+        add("S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), ref_p), mbar["S_L^+ apply"])
+        add("(I-L) S_L^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), mfs.PROJECT, prec)), ref_pp),
+            mbar["(I-L) S_L^+ apply"])
+        add("A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), ref_A), mbar["A gamma"])
+        add("A^T w", prec, rel_inf(_np(plan.matvec_adjoint(_dev(v), prec)), ref_AT), mbar["A^T w"])
         out, info = plan.solve(net, tol=1e-10 if prec == mfs.FP64 else 1e-5)
         assert info["status"] == mfs.MFS_OK
         out2, sigma = plan.extract(info["gamma"], info["s0"], want_sigma=True)
-        add("gamma", prec, rel_inf(_np(info["gamma"]), sol["gamma"]))
-        add("sigma", prec, rel_inf(_np(sigma), sol["sigma"]))
-        add("U / phi", prec, rel_inf(_np(out), sol["out"]))
+        add("gamma", prec, rel_inf(_np(info["gamma"]), sol["gamma"]), tb_["gamma"])
+        add("sigma", prec, rel_inf(_np(sigma), sol["sigma"]), tb_["sigma"])
+        add("U / phi", prec, rel_inf(_np(out), sol["out"]), tb_["out"])
         assert torch.equal(out, out2)
         # lambda = S_L^+ gamma with the FP64 factors (the extraction's own step)
         lam = plan.precond_apply(info["gamma"], 0, mfs.FP64)
-        add("lambda", prec, rel_inf(_np(lam), sol["lam"]))
+        add("lambda", prec, rel_inf(_np(lam), sol["lam"]), tb_["lam"])
         plan.close()
 
     # adjoint gradient of J = sum |U|^2 (Stokes) or sum phi^2 (Laplace) with respect to the centres
-    _, g_ref, _ = pr.velocity_loss_gradient(wl.net[0], tol=1e-12)
+    _, g_ref, info_ref = pr.velocity_loss_gradient(wl.net[0], tol=1e-12)
+    _, g_loose, _ = pr.velocity_loss_gradient(wl.net[0], tol=1e-8)
+    shape = (-1, 3) if kind == W.STOKES else (-1,)
+    wv, sg = info_ref["w"].reshape(shape), info_ref["sol"]["sigma"].reshape(shape)
+    cen = np.stack([b.centre for b in pr.bodies])
+    mgx, mgy = M.pair_grad(kind, pr.X, pr.trg_body, wv, pr.Y, pr.src_body, sg, cen)
+    gm = np.zeros((wl.n_body, 3))
+    np.add.at(gm, pr.trg_body, mgx)
+    np.add.at(gm, pr.src_body, mgy)
+    bar_dj = min(1e-5, M.bar(rel_inf(-gm, g_ref) + rel_inf(g_loose, g_ref)))
     for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(net, tol=tol)
         gc, _, _, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)
         assert st == mfs.MFS_OK
-        add("dJ/dc", prec, rel_inf(_np(gc), g_ref))
+        add("dJ/dc", prec, rel_inf(_np(gc), g_ref), bar_dj)
         plan.close()
     # the Dirichlet formulation (capacitance / resistance, Section 2)
     rp = O.ResistanceProblem.from_workload(wl)
@@ -151,26 +170,31 @@ def _rows(kind):
     r_ref_p = np.concatenate([rp.pinv_apply(k, rp.gblock(g, k)) for k in range(wl.n_body)])
     r_ref_A = rp.matvec(g)
     r_sol = rp.solve(data, tol=1e-12)
+    rbar = {"res: S^+ apply": M.bar(rel_inf(M.precondition(rp, g, project=False), r_ref_p)),
+            "res: A gamma": M.bar(rel_inf(M.matvec(rp, g), r_ref_A)), "res: rhs b": 1e-13}
+    # the Dirichlet problems are worse conditioned (more iterations); their mixed
+    # solve runs at tol 1e-6
+    rbar["res: F / q"] = M.solve_bars(rp, data, 1e-6, r_sol, ("out",), cap=1e-5)["out"]
     for prec in (mfs.FP64, mfs.MIXED):
         plan = mfs.Plan.from_workload(wl, prec, formulation=mfs.RESISTANCE)
         b, _ = plan.rhs(_dev(data), prec=prec)
-        add("res: rhs b", prec, rel_inf(_np(b), rb_ref))
-        add("res: S^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), r_ref_p))
-        add("res: A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), r_ref_A))
-        # the Dirichlet problems are worse conditioned (more iterations); their mixed bar is
-        # taken at tol 1e-6, as for the full-size solves
+        add("res: rhs b", prec, rel_inf(_np(b), rb_ref), rbar["res: rhs b"])
+        add("res: S^+ apply", prec, rel_inf(_np(plan.precond_apply(_dev(g), 0, prec)), r_ref_p),
+            rbar["res: S^+ apply"])
+        add("res: A gamma", prec, rel_inf(_np(plan.matvec(_dev(g), prec)), r_ref_A), rbar["res: A gamma"])
         out, info = plan.solve(_dev(data), tol=1e-10 if prec == mfs.FP64 else 1e-6)
         assert info["status"] == mfs.MFS_OK
-        add("res: F / q", prec, rel_inf(_np(out), r_sol["out"]))
+        add("res: F / q", prec, rel_inf(_np(out), r_sol["out"]), rbar["res: F / q"])
         plan.close()
     return rows
 
 
 def test_parity_report():
     rows = _rows(W.STOKES) + _rows(W.LAPLACE)
-    lines = [f"{'output':24s} {'kind':8s} {'prec':6s} {'rel_inf':>10s} {'bar':>8s}"]
+    lines = [f"{'output':24s} {'kind':8s} {'prec':6s} {'rel_inf':>10s} {'bar':>9s} {'bar/err':>8s}"]
     for name, kind, prec, err, bar in rows:
-        lines.append(f"{name:24s} {kind:8s} {prec:6s} {err:10.2e} {bar:8.0e}")
+        ratio = f"{bar / err:8.1f}" if err > 0 else "   exact"
+        lines.append(f"{name:24s} {kind:8s} {prec:6s} {err:10.2e} {bar:9.2e} {ratio}")
     text = "\n".join(lines)
     print("\n" + text)
     path = os.environ.get("MFS_PARITY_REPORT")
