@@ -191,6 +191,11 @@ struct Layout {
     uint64_t last_use = 0;
 };
 
+// launch shape of the standalone pair sums (one target per lane, at least this many
+// work items: a source split keeps the chip busy for single suspensions of a few
+// hundred bodies, as the plans' autotuner finds)
+constexpr int kStandaloneMinItems = 16384;
+
 struct Workspace {
     DevBuf centre, trg_off, src_ops, partial;
     std::vector<std::unique_ptr<Layout>> layouts;
@@ -289,7 +294,7 @@ int layout(Workspace &ws, int variant, int kind, int dim, double mu, int64_t n_s
     for (int64_t b = 0; b <= nb; ++b) out_ptr[b] = dim * body_trg_ptr[b];
     std::vector<int32_t> kob(std::max<int64_t>(1, nb), kind);
     MFS_TRY(build_p2p_items(l->pp, n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, out_ptr.data(), kob.data(), mu, 1,
-                            2048, s));
+                            kStandaloneMinItems, s));
     l->last_use = ++ws.clock;
     *out = l.get();
     ws.layouts.push_back(std::move(l));
@@ -1028,7 +1033,8 @@ int p2p_stokes_noalloc(int64_t n_sys, const int64_t *sys_body_ptr, const int64_t
     int64_t n_items = 0;
     int n_split = 1;
     MFS_TRY(generate_p2p_items(n_sys, sys_body_ptr, body_trg_ptr, body_src_ptr, nullptr, 3, nullptr, MFS_STOKES, mu, 1,
-                               2048, h.items, h.work, h.order, h.sorted, kNoAllocMaxItems, &n_items, &n_split));
+                               kStandaloneMinItems, h.items, h.work, h.order, h.sorted, kNoAllocMaxItems, &n_items,
+                               &n_split));
     // scratch layout (256-byte aligned pieces)
     const bool f32 = prec == MFS_MIXED;
     const size_t sz_ptr = align256((nb + 1) * sizeof(int32_t));
