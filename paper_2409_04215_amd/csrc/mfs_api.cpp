@@ -824,7 +824,7 @@ int factor_shapes(mfs_plan p, const mfs_plan_desc *d, const std::vector<int64_t>
         }
         if (p->factorization == MFS_FACTOR_QR) {
             // S_L = Q R (library QR): U^T <- Q^T, U <- Q, W <- R^-1, W^T <- R^-T
-            MFS_TRY(tau.reserve((size_t)B * n * sizeof(double)));
+            MFS_TRY(tau.reserve(qr_scratch_doubles(B, n) * sizeof(double)));
             MFS_TRY(qr_inverse_batched(B, SL.as<double>(), m, n, smn, Ub.as<double>(), smn, Vb.as<double>(), snn,
                                        tau.as<double>(), Sv.as<double>(), s));
             std::vector<double> rat(B);

@@ -300,11 +300,14 @@ struct GivensState {
 int launch_givens_init(const GivensState &st, hipStream_t s);
 
 // Batched FP64 Householder QR of column-major m x n matrices A (leading dimension m, m >= n,
-// n <= 8192), factor_kernels.hip: A is overwritten by R (upper triangle) and the reflectors,
-// Q (m x n, leading dimension m) and X = R^-1 (n x n, leading dimension n) are written, and
-// ratio[b] = 1 / (||R||_F ||R^-1||_F).  tau: [batch][n] scratch.
+// n <= 8192), factor_kernels.hip, blocked in panels of 32 columns (compact WY, trailing
+// updates and the accumulation of Q on the FP64 matrix cores): A is overwritten by R (upper
+// triangle) and the reflectors, Q (m x n, leading dimension m) and X = R^-1 (n x n, leading
+// dimension n) are written, and ratio[b] = 1 / (||R||_F ||R^-1||_F).  scratch: device
+// memory of qr_scratch_doubles(batch, n) doubles (tau, column norms and the panels' T factors).
+size_t qr_scratch_doubles(int batch, int n);
 int qr_inverse_batched(int batch, double *A, int m, int n, int64_t stride_a, double *Q, int64_t stride_q, double *X,
-                       int64_t stride_x, double *tau, double *ratio, hipStream_t s);
+                       int64_t stride_x, double *scratch, double *ratio, hipStream_t s);
 // Iteration j's last reduction (|w|^2 per system from the chunk partials, into nrm2, which
 // must be st.nrm2) and its Givens step, writing the iteration's status block.
 int launch_givens_step(const GivensState &st, const int32_t *sys_chunk_ptr, const double *partial, int ld_partial,
