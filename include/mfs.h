@@ -211,12 +211,15 @@ enum { MFS_MOBILITY = 0, MFS_RESISTANCE = 1 };
 /* Factorisation of the one-body blocks (Section 2.3, eq. (pseudo)).
  * MFS_FACTOR_SVD: S_L = U Sigma V^T by rocSOLVER's batched FP64 SVD
  *   (bidiagonal QR); the plan applies S_L^+ = (V Sigma^-1)(U^T .).
- * MFS_FACTOR_QR: S_L = Q R by the library's batched FP64 Householder QR;
+ * MFS_FACTOR_QR: S_L = Q R by the library's batched FP64 Householder QR
+ *   (blocked, compact WY form: trailing updates on the FP64 matrix cores);
  *   for full column rank S_L^+ = R^-1 Q^T, the same operator, applied in the
- *   same two steps ((R^-1)(Q^T .)), with R^-1 from triangular solves.  Much
- *   faster to build; mfs_plan_sizes then reports 1 / (||R||_F ||R^-1||_F),
- *   a lower bound of sigma_min / sigma_max, and the rank check uses that
- *   bound.  At most 8192 columns (3N Stokes, N Laplace) per block. */
+ *   same two steps ((R^-1)(Q^T .)), with R^-1 from triangular solves.  A
+ *   MFS_MIXED plan applies Q^T in FP32 and R^-1 in FP64 (R^-1 in FP32 would
+ *   cost the mixed operator accuracy on smooth inputs).  Much faster to
+ *   build; mfs_plan_sizes then reports 1 / (||R||_F ||R^-1||_F), a lower
+ *   bound of sigma_min / sigma_max, and the rank check uses that bound.  At
+ *   most 8192 columns (3N Stokes, N Laplace) per block. */
 enum { MFS_FACTOR_SVD = 0, MFS_FACTOR_QR = 1 };
 
 typedef struct {

@@ -812,6 +812,21 @@ int launch_rotate_out(const BodyView &bv, const void *in, bool in_f32, double *o
     return MFS_OK;
 }
 
+template <class S, class D>
+__global__ void cast_kernel(int64_t n, const S *__restrict__ in, D *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (D)in[i];
+}
+
+int launch_cast(int64_t n, const void *in, bool in_f32, void *out, hipStream_t s) {
+    if (n <= 0) return MFS_OK;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (in_f32) cast_kernel<float, double><<<grid, 256, 0, s>>>(n, (const float *)in, (double *)out);
+    else cast_kernel<double, float><<<grid, 256, 0, s>>>(n, (const double *)in, (float *)out);
+    MFS_HIP_TRY(hipGetLastError());
+    return MFS_OK;
+}
+
 int launch_project(const BodyView &bv, const void *lam, bool lam_f32, bool rotate, bool project, double *out64,
                    void *srcS, void *srcL, int src_prec, hipStream_t s) {
     if (bv.n_body == 0) return MFS_OK;

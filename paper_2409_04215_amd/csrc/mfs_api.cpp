@@ -1379,15 +1379,28 @@ namespace {
 
 // out64 = (I - L)? R S_L^+ R^T in   (gamma layout in, lambda layout out), and/or the
 // strengths of the forward pair-sum records of precision src_prec (src_prec < 0: none).
+// Mixed plans apply both factors in FP32, except the triangular factor R^-1 of a QR plan:
+// its entries are large and cancel on smooth inputs, so an FP32 copy errs at the solution
+// by about 2e-5 of the operator's output against 6e-7 for the SVD's W = V Sigma^+ (a Type
+// T block, cond 5.4e6), which costs refinement rounds; it is applied in FP64 instead.
 int precond_fwd(mfs_plan p, const double *in, int prec, bool project, double *out64, int src_prec, hipStream_t s) {
     BodyView bv = p->view();
-    const bool f32 = prec == MFS_MIXED;
+    bool f32 = prec == MFS_MIXED;
     if (f32) {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g32.ptr, true, false, s));
         MFS_TRY(launch_gemm_f32(p->gm[0].L, p->A32.as<float>(), p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(),
                                 p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
-        MFS_TRY(launch_gemm_f32(p->gm[1].L, p->A32.as<float>(), p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(),
-                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
+        if (p->factorization == MFS_FACTOR_QR) {
+            MFS_TRY(launch_cast(p->n_lambda, p->ws_l32a.ptr, true, p->ws_l64a.ptr, s));
+            MFS_TRY(launch_gemm_f64(p->gm[1].L, p->A64.as<double>(), p->ws_l64a.as<double>(),
+                                    p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(),
+                                    p->gpart64.as<double>(), s));
+            f32 = false;  // lambda in FP64
+        } else {
+            MFS_TRY(launch_gemm_f32(p->gm[1].L, p->A32.as<float>(), p->ws_l32a.as<float>(),
+                                    p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(),
+                                    p->gpart32.as<float>(), s));
+        }
     } else {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g64.ptr, false, false, s));
         MFS_TRY(launch_gemm_f64(p->gm[0].L, p->A64.as<double>(), p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(),
@@ -1413,9 +1426,18 @@ int precond_tr(mfs_plan p, const double *in, int prec, bool project, double *out
         src = p->ws_l64c.as<double>();
     }
     if (prec == MFS_MIXED) {
-        MFS_TRY(launch_rotate_in(bv, src, p->ws_l32a.ptr, true, true, s));
-        MFS_TRY(launch_gemm_f32(p->gm[2].L, p->A32.as<float>(), p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(),
-                                p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
+        if (p->factorization == MFS_FACTOR_QR) {  // R^-T in FP64 (see precond_fwd), then Q in FP32
+            MFS_TRY(launch_rotate_in(bv, src, p->ws_l64a.ptr, false, true, s));
+            MFS_TRY(launch_gemm_f64(p->gm[2].L, p->A64.as<double>(), p->ws_l64a.as<double>(),
+                                    p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(),
+                                    p->gpart64.as<double>(), s));
+            MFS_TRY(launch_cast(p->n_lambda, p->ws_l64b.ptr, false, p->ws_l32b.ptr, s));
+        } else {
+            MFS_TRY(launch_rotate_in(bv, src, p->ws_l32a.ptr, true, true, s));
+            MFS_TRY(launch_gemm_f32(p->gm[2].L, p->A32.as<float>(), p->ws_l32a.as<float>(),
+                                    p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(),
+                                    p->gpart32.as<float>(), s));
+        }
         MFS_TRY(launch_gemm_f32(p->gm[3].L, p->A32.as<float>(), p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(),
                                 p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(), p->gpart32.as<float>(), s));
         return launch_rotate_out(bv, p->ws_g32.ptr, true, out, false, s);

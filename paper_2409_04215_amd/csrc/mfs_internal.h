@@ -228,6 +228,8 @@ struct BodyView {
 int launch_rotate_in(const BodyView &bv, const double *in, void *out, bool out_f32, bool lam_layout, hipStream_t s);
 // shape frame (float or double) -> world frame fp64
 int launch_rotate_out(const BodyView &bv, const void *in, bool in_f32, double *out, bool lam_layout, hipStream_t s);
+// out[i] = in[i] converted float -> double (in_f32) or double -> float, i < n
+int launch_cast(int64_t n, const void *in, bool in_f32, void *out, hipStream_t s);
 // lam (lambda layout) -> optionally rotated to the world frame, optionally (I - L); written to out64
 // (may alias lam when lam is fp64 and rotate is false) and/or into the pair-sum source records
 // srcS / srcL (chosen by body kind; either may be null) of precision src_prec

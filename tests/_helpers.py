@@ -12,6 +12,16 @@ def rel_inf(x, ref) -> float:
     return float(np.abs(x - ref).max() / (den if den > 0 else 1.0))
 
 
+def tight_reference(path):
+    """A stored solution at GMRES tol 1e-13 (tests/golden/make_golden.py
+    e100_tight) and, from its header, the final residual estimate rho of the
+    oracle's solve at tol 1e-10 and that solve's output error err against it."""
+    import re
+    head = "".join(line for line in open(path) if line.startswith("#"))
+    m = re.search(r"rho ([0-9.eE+-]+) err ([0-9.eE+-]+)", head)
+    return np.loadtxt(path).reshape(-1), float(m.group(1)), float(m.group(2))
+
+
 def structure(wl):
     """Host structure arrays of a workload: sys_body_ptr, body_trg_ptr, body_src_ptr."""
     n_trg = [wl.shapes[s].trg.shape[0] for s in wl.shape_of_body]

@@ -3,8 +3,10 @@ this script.  Calls only oracle/ and the seeded input generators.
 
     python tests/golden/make_golden.py            # ellipsoids_100 mobility / elastance (minutes)
     python tests/golden/make_golden.py two_way    # ellipsoids_100 resistance -> mobility (2-way error)
+    python tests/golden/make_golden.py e100_tight # ellipsoids_100 at GMRES tol 1e-13 (minutes)
     python tests/golden/make_golden.py rows_10000 # 10^4 Type T case: 1000 sampled rows (tens of minutes)
     python tests/golden/make_golden.py rows_10000_model  # the float32 model on 100 of those rows
+    python tests/golden/make_golden.py rows_10000_model64 rows_1000_model64  # the float64 model of the stored rows
     python tests/golden/make_golden.py rows_1000  # ellipsoids_1000: 2000 sampled rows, oracle and float32 model
     python tests/golden/make_golden.py batched    # batched_64: a stated subset of the 64 systems (~1.5 h)
     python tests/golden/make_golden.py e1000_laplace | e1000_stokes   # ellipsoids_1000 (~1 h / ~4 h)
@@ -92,6 +94,30 @@ def e100():
                f"Written by tests/golden/make_golden.py (oracle only).")
         np.savetxt(os.path.join(HERE, name), out, fmt="%.17e", header=hdr)
         print(name, sol["iters"], f"{dt:.0f}s", flush=True)
+
+
+def e100_tight():
+    """ellipsoids_100 solved to GMRES tol 1e-13: a reference whose own stopping
+    error lies far below that of a solve at tol 1e-10.  The header keeps the
+    tol-1e-10 solve's final residual estimate rho and its output error
+    against this reference, err: err / rho is the oracle's ratio of output
+    error to relative residual near convergence, which sizes the FP64 bar of
+    a solve at tol 1e-10 from the residual it ends at."""
+    for kind, name in ((W.STOKES, "ellipsoids_100_stokes_U_tight.txt"), (W.LAPLACE, "ellipsoids_100_laplace_phi_tight.txt")):
+        wl = W.ellipsoids_100(kind)
+        pr = O.Problem.from_workload(wl)
+        t0 = time.time()
+        s10 = pr.solve(wl.net[0], tol=TOL)
+        s13 = pr.solve(wl.net[0], tol=1e-13)
+        dt = time.time() - t0
+        out = np.asarray(s13["out"]).reshape(wl.n_body, -1)
+        err = float(np.abs(np.asarray(s10["out"]) - np.asarray(s13["out"])).max() / np.abs(np.asarray(s13["out"])).max())
+        hdr = (f"oracle solution of the seeded ellipsoids_100 workload ({'Stokes mobility' if kind else 'Laplace elastance'})"
+               f" at GMRES tol 1e-13 ({s13['iters']} iterations, final residual estimate {s13['hist'][-1]:.3e});\n"
+               f"tol-1e-10 solve: rho {s10['hist'][-1]:.6e} err {err:.6e} ({s10['iters']} iterations); {dt:.0f} s.\n"
+               f"Written by tests/golden/make_golden.py e100_tight (oracle only).")
+        np.savetxt(os.path.join(HERE, name), out, fmt="%.17e", header=hdr)
+        _log(name, s13["iters"], s10["hist"][-1], err, f"{dt:.0f}s")
 
 
 def e1000(kind):
@@ -223,7 +249,48 @@ def rows_10000_model():
     _log("10^4 model rows stored")
 
 
-JOBS = {"rows_1000": rows_1000, "rows_10000_model": rows_10000_model, "two_way": two_way, "rows_10000": rows_10000, "batched": batched,
+def _model64_rows(pr, wl, rows, g, sm):
+    """Right-hand side and both matvecs on `rows` by the float64 model
+    (oracle/fp32_model.py with dt = float64: another summation order and an
+    independent FP64 SVD of S_L), which sizes the FP64 bars."""
+    F64 = np.float64
+    return [M.rhs(pr, wl.net[0], rows=rows, dt=F64), M.matvec(pr, g, rows=rows, dt=F64),
+            M.matvec(pr, sm, rows=rows, dt=F64)]
+
+
+def rows_1000_model64():
+    """The float64 model of ellipsoids_1000's stored rows (both kinds)."""
+    for kind, name in ((W.STOKES, "stokes"), (W.LAPLACE, "laplace")):
+        t0 = time.time()
+        rows = np.loadtxt(os.path.join(HERE, f"ellipsoids_1000_{name}_rows.txt"))[:, 0].astype(np.int64)
+        wl = W.ellipsoids_1000(kind)
+        pr = O.Problem.from_workload(wl)
+        cols = _model64_rows(pr, wl, rows, W.random_vector(pr.n_gamma, 82), W.smooth_vector(wl, 83))
+        d = 3 if kind == W.STOKES else 1
+        tab = np.concatenate([rows[:, None].astype(np.float64)] + [c.reshape(-1, d) for c in cols], axis=1)
+        hdr = (f"the float64 model (oracle/fp32_model.py, dt = float64) of the rows of ellipsoids_1000_{name}_rows.txt;\n"
+               f"columns: row, then ({d} each) b, A g, A s (the same vectors).\n"
+               f"{time.time() - t0:.0f} s.  Written by tests/golden/make_golden.py rows_1000_model64 (oracle/ only).")
+        np.savetxt(os.path.join(HERE, f"ellipsoids_1000_{name}_model64_rows.txt"), tab, fmt="%.17e", header=hdr)
+        _log(f"ellipsoids_1000 {name} float64 model rows stored, {time.time() - t0:.0f} s")
+
+
+def rows_10000_model64():
+    """The float64 model of the 10^4 case's first 100 stored rows."""
+    t0 = time.time()
+    rows = np.loadtxt(os.path.join(HERE, "ellipsoids_10000_rows.txt"))[:100, 0].astype(np.int64)
+    wl = W.ellipsoids_10000(W.STOKES)
+    pr = O.Problem.from_workload(wl)
+    cols = _model64_rows(pr, wl, rows, W.random_vector(pr.n_gamma, 87), W.smooth_vector(wl, 88))
+    out = np.concatenate([rows[:, None].astype(np.float64)] + [c.reshape(-1, 3) for c in cols], axis=1)
+    hdr = ("the float64 model (oracle/fp32_model.py, dt = float64) of the first 100 stored rows of "
+           "ellipsoids_10000_rows.txt;\ncolumns: row, right-hand side b (3), A g (3), A s (3) (the same vectors).\n"
+           f"{time.time() - t0:.0f} s.  Written by tests/golden/make_golden.py rows_10000_model64 (oracle/ only).")
+    np.savetxt(os.path.join(HERE, "ellipsoids_10000_model64_rows.txt"), out, fmt="%.17e", header=hdr)
+    _log("10^4 float64 model rows stored")
+
+
+JOBS = {"e100_tight": e100_tight, "rows_1000_model64": rows_1000_model64, "rows_10000_model64": rows_10000_model64, "rows_1000": rows_1000, "rows_10000_model": rows_10000_model, "two_way": two_way, "rows_10000": rows_10000, "batched": batched,
         "e1000_laplace": lambda: e1000(W.LAPLACE), "e1000_stokes": lambda: e1000(W.STOKES)}
 
 

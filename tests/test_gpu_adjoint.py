@@ -5,9 +5,14 @@ matvec) against the oracle's adjoint gradient and against central finite
 differences of forward solves.
 
 Loss J = sum_k |U^(k)|^2 (velocities and angular velocities), so
-dJ/dU = 2 U.  Tolerances (rel_inf over the (P, 3) gradient):
-* FP64 plan, tol 1e-12 on both solves: 1e-8 against the oracle.
-* MIXED plan, tol 1e-8 (FP64 true-residual refinement on both solves): 1e-5.
+dJ/dU = 2 U.  Tolerances (rel_inf over the (P, 3) gradient), against the
+oracle's gradient with both solves at tol 1e-14:
+* FP64 plan, tol 1e-12 on both solves; MIXED plan, tol 1e-8 (FP64
+  true-residual refinement on both solves): 4 x (the error of the model of
+  the gradient's pair sums in the plan's precision, float64 or float32, on
+  the oracle's adjoint solution and strengths + the oracle's own error when
+  both its solves stop at the plan's tol), at most 1e-5
+  (oracle/fp32_model.py gradient_bars); the same for dJ/d(net).
 * Finite differences (h = 1e-5, FP64 solves at tol 1e-12) of the directional
   derivative along a unit direction v: |fd - g.v| <= 1e-6 |g|_2 for the FP64
   gradient and 1e-5 |g|_2 for the mixed one (the error of a directional
@@ -20,9 +25,12 @@ import torch
 
 import mfs_workloads as W
 from oracle import mfs_oracle as O
+from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
+
+F64 = np.float64
 
 
 def _mfs():
@@ -47,29 +55,34 @@ def _gpu_grad(wl, prec, tol):
 def test_gradient_matches_oracle_small():
     mfs = _mfs()
     wl = W.small_cluster(3, W.STOKES, 60, 130, seed=31, axes=(1.0, 1.0, 1.0))
-    J_ref, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    pr = O.Problem.from_workload(wl)
+    g_ref, info, b64 = M.gradient_bars(pr, wl.net[0], 1e-12, F64)
+    _, _, bmx = M.gradient_bars(pr, wl.net[0], 1e-8, M.F32)
+    J_ref = float(np.sum(np.asarray(info["sol"]["out"]) ** 2))
     J64, g64, _ = _gpu_grad(wl, mfs.FP64, 1e-12)
     Jmx, gmx, _ = _gpu_grad(wl, mfs.MIXED, 1e-8)
-    print("J", J_ref, J64, Jmx, "grad err fp64", rel_inf(g64, g_ref), "mixed", rel_inf(gmx, g_ref))
+    print("J", J_ref, J64, Jmx, "grad err fp64", rel_inf(g64, g_ref), b64, "mixed", rel_inf(gmx, g_ref), bmx)
     assert abs(J64 - J_ref) <= 1e-10 * J_ref
-    assert rel_inf(g64, g_ref) <= 1e-8
-    assert rel_inf(gmx, g_ref) <= 1e-5
+    assert rel_inf(g64, g_ref) <= b64["centre"]
+    assert rel_inf(gmx, g_ref) <= bmx["centre"]
 
 
 def test_gradient_ellipsoids_matches_oracle():
     mfs = _mfs()
     wl = W.small_cluster(4, W.STOKES, 45, 301, seed=32)
-    _, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    pr = O.Problem.from_workload(wl)
+    g_ref, _, b64 = M.gradient_bars(pr, wl.net[0], 1e-12, F64)
+    _, _, bmx = M.gradient_bars(pr, wl.net[0], 1e-8, M.F32)
     _, g64, _ = _gpu_grad(wl, mfs.FP64, 1e-12)
     _, gmx, _ = _gpu_grad(wl, mfs.MIXED, 1e-8)
-    assert rel_inf(g64, g_ref) <= 1e-8
-    assert rel_inf(gmx, g_ref) <= 1e-5
+    assert rel_inf(g64, g_ref) <= b64["centre"]
+    assert rel_inf(gmx, g_ref) <= bmx["centre"]
 
 
 def test_autograd_function():
     mfs = _mfs()
     wl = W.small_cluster(3, W.STOKES, 60, 130, seed=33, axes=(1.0, 1.0, 1.0))
-    _, g_ref, info = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
+    g_ref, info, bars = M.gradient_bars(O.Problem.from_workload(wl), wl.net[0], 1e-8, M.F32)
     spec = dict(precision=mfs.MIXED, sys_body_ptr=wl.sys_body_ptr, sys_kind=wl.sys_kind, rot=wl.rot,
                 shape_of_body=wl.shape_of_body, shape_src=[s.src for s in wl.shapes],
                 shape_trg=[s.trg for s in wl.shapes], mu=1.0, tol=1e-8)
@@ -80,8 +93,8 @@ def test_autograd_function():
     loss.backward()
     print("autograd: centre grad err", rel_inf(centre.grad.cpu().numpy(), g_ref),
           "net grad err", rel_inf(net.grad.cpu().numpy(), info["grad_net"].reshape(-1)))
-    assert rel_inf(centre.grad.cpu().numpy(), g_ref) <= 1e-5
-    assert rel_inf(net.grad.cpu().numpy(), info["grad_net"].reshape(-1)) <= 1e-5
+    assert rel_inf(centre.grad.cpu().numpy(), g_ref) <= bars["centre"]
+    assert rel_inf(net.grad.cpu().numpy(), info["grad_net"].reshape(-1)) <= bars["net"]
 
 
 @pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
@@ -93,17 +106,18 @@ def test_net_gradient_matches_oracle(kind):
     gradient requested is refused."""
     mfs = _mfs()
     wl = W.small_cluster(4, kind, 45, 301, seed=35)
-    _, g_ref, info_ref = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
-    gn_ref = info_ref["grad_net"].reshape(-1)
-    for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-8, 1e-5)):
+    pr = O.Problem.from_workload(wl)
+    for prec, tol, dt in ((mfs.FP64, 1e-12, F64), (mfs.MIXED, 1e-8, M.F32)):
+        g_ref, info_ref, bars = M.gradient_bars(pr, wl.net[0], tol, dt)
+        gn_ref = info_ref["grad_net"].reshape(-1)
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
         gc, gn, iters, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol,
                                                          want_net=True)
         assert st == mfs.MFS_OK
         e = (rel_inf(gc.cpu().numpy(), g_ref), rel_inf(gn.cpu().numpy(), gn_ref))
-        print(f"kind={kind} prec={prec} centre grad err {e[0]:.2e} net grad err {e[1]:.2e} iters {iters}")
-        assert max(e) <= bar
+        print(f"kind={kind} prec={prec} centre grad err {e[0]:.2e} net grad err {e[1]:.2e} iters {iters}", bars)
+        assert e[0] <= bars["centre"] and e[1] <= bars["net"]
         _, gn2, _, _, st = plan.gmres_solve_backward(info["gamma"], None, 2.0 * out, tol=tol, want_centre=False,
                                                      want_net=True)
         assert st == mfs.MFS_OK and rel_inf(gn2.cpu().numpy(), gn.cpu().numpy()) <= 1e-12
@@ -150,8 +164,11 @@ def test_elastance_gradient_matches_oracle():
     oracle's adjoint gradient (itself pinned by finite differences)."""
     mfs = _mfs()
     wl = W.small_cluster(4, W.LAPLACE, 45, 301, seed=34)
-    J_ref, g_ref, _ = O.Problem.from_workload(wl).velocity_loss_gradient(wl.net[0], tol=1e-12)
-    for prec, tol, bar in ((mfs.FP64, 1e-12, 1e-8), (mfs.MIXED, 1e-8, 1e-5)):
+    pr = O.Problem.from_workload(wl)
+    for prec, tol, dt in ((mfs.FP64, 1e-12, F64), (mfs.MIXED, 1e-8, M.F32)):
+        g_ref, info_ref, bars = M.gradient_bars(pr, wl.net[0], tol, dt)
+        J_ref = float(np.sum(np.asarray(info_ref["sol"]["out"]) ** 2))
+        bar = bars["centre"]
         plan = mfs.Plan.from_workload(wl, prec)
         out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
         g, _, iters, relres, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol)

@@ -9,6 +9,12 @@
   the outputs are exactly 0 and the status is OK.
 * Bodies of one system with different N and M (shapes of different sizes),
   ragged against the 64-target blocks: matvec and solve against the oracle.
+
+Bars: 4 x the error of the model of the plan's precision (float32 for
+mixed, float64 for FP64 plans; oracle/fp32_model.py) for operator outputs;
+solve outputs by solve_bars (stopping and operator limits), and the GPU
+solution's residual under the oracle's b and A at most the tolerance plus 4 x
+the model's right-hand-side error.
 """
 import numpy as np
 import pytest
@@ -20,6 +26,8 @@ from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
+
+F64 = np.float64
 
 
 def _mfs():
@@ -38,17 +46,19 @@ def test_one_body_operator_is_identity(kind):
     pr = O.Problem.from_workload(wl)
     g = _dev(W.random_vector(pr.n_gamma, 122))
     sol = pr.solve(wl.net[0], tol=1e-13)
-    # one body: A = I and gamma = b, so the mixed outputs carry the mixed right-hand
-    # side's error only; bar: 4 x the error of the outputs of the float32 model's b
-    b32 = M.rhs(pr, wl.net[0])
-    bar_mx = M.bar(rel_inf(pr.extract(b32, sol["s0"])[0], sol["out"]))
+    # one body: A = I and gamma = b, so the outputs carry the right-hand side's error
+    # and the extraction's only; bar: 4 x the error of the outputs of the model's b
+    # (float32: extracted with FP64 factors, as the mixed plan extracts; float64: with
+    # the model's own FP64 factors)
+    bar_mx = M.bar(rel_inf(pr.extract(M.rhs(pr, wl.net[0]), sol["s0"])[0], sol["out"]))
+    bar64 = M.bar(rel_inf(M.extract(pr, M.rhs(pr, wl.net[0], dt=F64), sol["s0"])[0], sol["out"]))
     for prec in (mfs.FP64, mfs.MIXED):
         plan = mfs.Plan.from_workload(wl, prec)
         assert torch.equal(plan.matvec(g, mfs.FP64), g)
         assert torch.equal(plan.matvec_adjoint(g, mfs.FP64), g)
         out, info = plan.solve(_dev(net_flat(wl)), tol=1e-10)
         assert info["status"] == mfs.MFS_OK and info["iters"][0] <= 2
-        assert rel_inf(out.cpu().numpy(), sol["out"]) <= (1e-10 if prec == mfs.FP64 else bar_mx)
+        assert rel_inf(out.cpu().numpy(), sol["out"]) <= (bar64 if prec == mfs.FP64 else bar_mx)
         plan.close()
 
 
@@ -66,10 +76,13 @@ def test_batch_with_an_empty_system():
     out, info = plan.solve(net, tol=1e-10)
     assert info["status"] == mfs.MFS_OK
     assert info["iters"][1] == 0 and info["relres"][1] == 0.0
-    ref_a = O.Problem.from_workload(a).solve(a.net[0], tol=1e-12)["out"]
-    ref_b = O.Problem.from_workload(b).solve(b.net[0], tol=1e-12)["out"]
     got = out.cpu().numpy().reshape(-1, 6)
-    assert rel_inf(got[:3], ref_a) <= 1e-8 and rel_inf(got[3:], ref_b) <= 1e-8
+    gam = info["gamma"].cpu().numpy()
+    pa, pb = O.Problem.from_workload(a), O.Problem.from_workload(b)
+    for p_, w_, g_, o_ in ((pa, a, gam[:pa.n_gamma], got[:3]), (pb, b, gam[pa.n_gamma:], got[3:])):
+        sol = p_.solve(w_.net[0], tol=1e-12)
+        bars = M.solve_bars(p_, w_.net[0], 1e-10, sol, dt=F64, gamma=g_)
+        assert bars["residual"] <= bars["residual_bound"] and rel_inf(o_, sol["out"]) <= bars["out"]
     plan.close()
 
 
@@ -97,13 +110,14 @@ def test_bodies_of_different_sizes_in_one_system():
     g = W.random_vector(pr.n_gamma, 127)
     ref = pr.matvec(g)
     sol = pr.solve(base.net[0], tol=1e-12)
-    mixed = (M.bar(rel_inf(M.matvec(pr, g), ref)), 1e-7, M.solve_bars(pr, base.net[0], 1e-7, sol, cap=1e-5)["out"])
-    for prec, tol_mv, tol_s, bar in ((mfs.FP64, 1e-10, 1e-10, 1e-8), (mfs.MIXED, *mixed)):
+    for prec, dt, tol_s in ((mfs.FP64, F64, 1e-10), (mfs.MIXED, M.F32, 1e-7)):
         plan = mfs.Plan.from_workload(base, prec)
-        assert rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref) <= tol_mv
+        assert rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref) <= M.bar(rel_inf(M.matvec(pr, g, dt=dt), ref))
         out, info = plan.solve(_dev(net_flat(base)), tol=tol_s)
         assert info["status"] == mfs.MFS_OK
-        assert rel_inf(out.cpu().numpy(), sol["out"]) <= bar
+        bars = M.solve_bars(pr, base.net[0], tol_s, sol, cap=1e-5, dt=dt, gamma=info["gamma"].cpu().numpy())
+        assert bars["residual"] <= bars["residual_bound"]
+        assert rel_inf(out.cpu().numpy(), sol["out"]) <= bars["out"]
         plan.close()
 
 
@@ -125,13 +139,18 @@ def test_many_systems_and_one_iteration():
     out, info = plan.solve(net, tol=1e-10)
     assert info["status"] == mfs.MFS_OK
     got = out.cpu().numpy()
-    off = 0
+    gam = info["gamma"].cpu().numpy()
+    off = goff = 0
     for s, p in enumerate(parts):
         m = 2 * (6 if kinds[s] == W.STOKES else 1)
+        pr = O.Problem.from_workload(p)
         if s % 37 == 0:
-            ref = O.Problem.from_workload(p).solve(p.net[0], tol=1e-12)["out"]
-            assert rel_inf(got[off:off + m], np.asarray(ref).reshape(-1)) <= 1e-8, s
+            sol = pr.solve(p.net[0], tol=1e-12)
+            bars = M.solve_bars(pr, p.net[0], 1e-10, sol, dt=F64, gamma=gam[goff:goff + pr.n_gamma])
+            assert bars["residual"] <= bars["residual_bound"], s
+            assert rel_inf(got[off:off + m], np.asarray(sol["out"]).reshape(-1)) <= bars["out"], s
         off += m
+        goff += pr.n_gamma
     # max_iter = 1: one Arnoldi step, x = y_0 v_0 with y_0 = g_0 / R_00
     b, _ = plan.rhs(net)
     g1, it1, rr1, st1 = plan.gmres_solve(b, tol=1e-12, max_iter=1)

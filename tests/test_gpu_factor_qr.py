@@ -5,18 +5,21 @@ For full column rank this is the pseudo-inverse the SVD gives (Section 2.3),
 so a QR plan must meet the same bars against the oracle (which uses the SVD)
 as an SVD plan, and agree with an SVD plan to FP64 rounding amplified by the
 conditioning of S_L:
-* S_L^+ apply and Ag: FP64 1e-10; mixed 4 x the error of the float32 model
-  with the QR plan's FP32 factors Q^T and R^-1 (oracle/fp32_model.py);
-* solves: FP64 at tol 1e-10 within 1e-8 of the oracle; mixed at tol t within
-  4 x the larger of the stopping-residual limit and the float32-operator
-  limit of oracle/fp32_model.py solve_bars, at most 1e-5; ellipsoids_100 against
-  the stored oracle solutions as in the full-size tests (mixed at the
-  benchmark tolerance 1e-5: 1e-5);
+* S_L^+ apply and Ag: 4 x the error of the model with a QR plan's factors
+  Q^T and R^-1 (oracle/fp32_model.py: float32 factors and products for
+  mixed; an independent FP64 QR and R^-1 for FP64);
+* solves: at tol t within 4 x the larger of the stopping limit and the
+  operator limit of oracle/fp32_model.py solve_bars (QR model of the plan's
+  precision), at most 1e-5, and the GPU solution's residual under the
+  oracle's b and A at most t plus 4 x the model's right-hand-side error;
+  ellipsoids_100 against the stored oracle solutions as in the full-size
+  tests;
 * the reported ratio 1/(|R|_F |R^-1|_F) lies between sigma_min/sigma_max / n
   and sigma_min/sigma_max (n = columns);
 * a rank-deficient block (two proxies at one point) is refused.
 """
 import os
+import time
 
 import numpy as np
 import pytest
@@ -25,9 +28,10 @@ import torch
 import mfs_workloads as W
 from oracle import mfs_oracle as O
 from oracle import fp32_model as M
-from tests._helpers import net_flat, rel_inf
+from tests._helpers import net_flat, rel_inf, tight_reference
 
 pytestmark = pytest.mark.gpu
+F64 = np.float64
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -49,10 +53,10 @@ def test_qr_plan_matches_oracle_and_svd_plan(kind):
     ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
     ref_A = pr.matvec(g)
     sol = pr.solve(wl.net[0], tol=1e-12)
-    mixed = (M.bar(rel_inf(M.precond_apply(pr, g, qr=True), ref_p)), M.bar(rel_inf(M.matvec(pr, g, qr=True), ref_A)),
-             1e-7, M.solve_bars(pr, wl.net[0], 1e-7, sol, cap=1e-5, qr=True)["out"])
     svd = mfs.Plan.from_workload(wl, mfs.FP64)
-    for prec, tol_p, tol_A, solve_tol, bar in ((mfs.FP64, 1e-10, 1e-10, 1e-10, 1e-8), (mfs.MIXED, *mixed)):
+    for prec, dt, solve_tol in ((mfs.FP64, F64, 1e-10), (mfs.MIXED, M.F32, 1e-7)):
+        tol_p = M.bar(rel_inf(M.precond_apply(pr, g, qr=True, dt=dt), ref_p))
+        tol_A = M.bar(rel_inf(M.matvec(pr, g, qr=True, dt=dt), ref_A))
         qr = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
         e = (rel_inf(qr.precond_apply(_dev(g), 0, prec).cpu().numpy(), ref_p),
              rel_inf(qr.matvec(_dev(g), prec).cpu().numpy(), ref_A))
@@ -61,10 +65,13 @@ def test_qr_plan_matches_oracle_and_svd_plan(kind):
         print(kind, prec, "S_L^+ apply, A g", e, "solve", es, "iters", info["iters"], "ratio bound", qr.min_sigma_ratio,
               "svd ratio", svd.min_sigma_ratio)
         assert e[0] <= tol_p and e[1] <= tol_A
-        assert info["status"] == mfs.MFS_OK and es <= bar
+        assert info["status"] == mfs.MFS_OK
+        bars = M.solve_bars(pr, wl.net[0], solve_tol, sol, cap=1e-5, qr=True, dt=dt, gamma=info["gamma"].cpu().numpy())
+        assert bars["residual"] <= bars["residual_bound"] and es <= bars["out"]
         if prec == mfs.FP64:
+            # two FP64 factorisations of S_L: each matvec within its own bar of the oracle's
             d = rel_inf(qr.matvec(_dev(g), mfs.FP64).cpu().numpy(), svd.matvec(_dev(g), mfs.FP64).cpu().numpy())
-            assert d <= 1e-10
+            assert d <= tol_A + M.bar(rel_inf(M.matvec(pr, g, dt=F64), ref_A))
             ncol = (3 if kind == W.STOKES else 1) * wl.shapes[0].src.shape[0]
             assert svd.min_sigma_ratio / ncol <= qr.min_sigma_ratio <= svd.min_sigma_ratio * (1 + 1e-9)
         qr.close()
@@ -72,18 +79,20 @@ def test_qr_plan_matches_oracle_and_svd_plan(kind):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("kind,fname", [(W.STOKES, "ellipsoids_100_stokes_U.txt"),
-                                        (W.LAPLACE, "ellipsoids_100_laplace_phi.txt")])
+@pytest.mark.parametrize("kind,fname", [(W.STOKES, "ellipsoids_100_stokes_U_tight.txt"),
+                                        (W.LAPLACE, "ellipsoids_100_laplace_phi_tight.txt")])
 def test_qr_plan_ellipsoids_100_vs_stored_oracle(kind, fname):
+    """Against the oracle's solution at tol 1e-13, with the bars of the SVD
+    plan's test (tests/test_gpu_fullsize.py)."""
     mfs = _mfs()
     wl = W.ellipsoids_100(kind)
-    ref = np.loadtxt(os.path.join(GOLDEN, fname)).reshape(-1)
+    ref, rho, err10 = tight_reference(os.path.join(GOLDEN, fname))
     net = _dev(net_flat(wl))
-    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-5, 1e-5)):
+    for prec, tol, bar in ((mfs.FP64, 1e-10, M.bar(err10 / rho * M.STOP * 1e-10)), (mfs.MIXED, 1e-5, 1e-5)):
         plan = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
         out, info = plan.solve(net, tol=tol)
         e = rel_inf(out.cpu().numpy(), ref)
-        print(f"QR kind={kind} prec={prec} tol={tol:g} iters={info['iters']} err={e:.2e}")
+        print(f"QR kind={kind} prec={prec} tol={tol:g} iters={info['iters']} err={e:.2e} bar={bar:.2e}")
         assert info["status"] == mfs.MFS_OK and e <= bar
         plan.close()
 
@@ -111,13 +120,19 @@ def test_type_t_cluster_both_factorizations():
     ref = sol["out"]
     net = _dev(net_flat(wl))
     for fact in (mfs.FACTOR_SVD, mfs.FACTOR_QR):
-        mixed_bar = M.solve_bars(pr, wl.net[0], 1e-6, sol, cap=1e-5, qr=fact == mfs.FACTOR_QR)["out"]
-        for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, 1e-6, mixed_bar)):
+        for prec, tol, dt in ((mfs.FP64, 1e-10, F64), (mfs.MIXED, 1e-6, M.F32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             plan = mfs.Plan.from_workload(wl, prec, factorization=fact)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
             out, info = plan.solve(net, tol=tol)
             e = rel_inf(out.cpu().numpy(), ref)
-            print("type T", "QR" if fact else "SVD", prec, "iters", info["iters"], "err", e, "ratio", plan.min_sigma_ratio)
-            assert info["status"] == mfs.MFS_OK and e <= bar
+            bars = M.solve_bars(pr, wl.net[0], tol, sol, cap=1e-5, qr=fact == mfs.FACTOR_QR, dt=dt,
+                                gamma=info["gamma"].cpu().numpy())
+            print("type T", "QR" if fact else "SVD", prec, "iters", info["iters"], "err", e, bars,
+                  "ratio", plan.min_sigma_ratio, f"plan creation {t_setup:.3f} s", flush=True)
+            assert info["status"] == mfs.MFS_OK and bars["residual"] <= bars["residual_bound"] and e <= bars["out"]
             plan.close()
 
 
@@ -130,11 +145,11 @@ def test_qr_resistance_plan(kind):
     data = rng.standard_normal((4, 6)) if kind == W.STOKES else rng.standard_normal(4)
     rp = O.ResistanceProblem.from_workload(wl)
     sol = rp.solve(data, tol=1e-12)
-    for prec, tol, bar in ((mfs.FP64, 1e-10, 1e-8),
-                           (mfs.MIXED, 1e-7, M.solve_bars(rp, data, 1e-7, sol, cap=1e-5, qr=True)["out"])):
+    for prec, tol, dt in ((mfs.FP64, 1e-10, F64), (mfs.MIXED, 1e-7, M.F32)):
         plan = mfs.Plan.from_workload(wl, prec, formulation=mfs.RESISTANCE, factorization=mfs.FACTOR_QR)
         out, info = plan.solve(_dev(data), tol=tol)
         e = rel_inf(out.cpu().numpy(), np.asarray(sol["out"]).reshape(-1))
-        print("resistance QR", kind, prec, "err", e)
-        assert info["status"] == mfs.MFS_OK and e <= bar
+        bars = M.solve_bars(rp, data, tol, sol, cap=1e-5, qr=True, dt=dt, gamma=info["gamma"].cpu().numpy())
+        print("resistance QR", kind, prec, "err", e, bars)
+        assert info["status"] == mfs.MFS_OK and bars["residual"] <= bars["residual_bound"] and e <= bars["out"]
         plan.close()

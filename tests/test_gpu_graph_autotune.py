@@ -5,7 +5,8 @@
   eager solve bit for bit (the same kernels in the same order on the same
   data; only the Krylov column is staged into a fixed buffer first).
 * Autotune: after the pair-sum launch shape changes, the matvec still agrees
-  with the oracle (tolerances of test_gpu_operator) and solves converge.
+  with the oracle (the bars of test_gpu_operator: 4 x the error of the
+  model of each precision) and solves converge.
 """
 import numpy as np
 import pytest
@@ -17,6 +18,8 @@ from oracle import fp32_model as M
 from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
+
+F64 = np.float64
 
 
 def _mfs():
@@ -68,13 +71,17 @@ def test_autotune_keeps_results(kind):
     plan = mfs.Plan.from_workload(wl, mfs.MIXED)
     tpl, mi, ms = plan.autotune(mfs.MIXED, reps=2)
     assert abs(tpl) in (1, 2) and mi in (1024, 2048, 4096, 8192, 16384) and ms > 0
-    assert rel_inf(plan.matvec(_dev(g), mfs.FP64).cpu().numpy(), ref) <= 1e-10
+    ref_t = pr.matvec_T(g)
+    assert rel_inf(plan.matvec(_dev(g), mfs.FP64).cpu().numpy(), ref) <= M.bar(rel_inf(M.matvec(pr, g, dt=F64), ref))
     assert rel_inf(plan.matvec(_dev(g), mfs.MIXED).cpu().numpy(), ref) <= M.bar(rel_inf(M.matvec(pr, g), ref))
-    assert rel_inf(plan.matvec_adjoint(_dev(g), mfs.FP64).cpu().numpy(), pr.matvec_T(g)) <= 1e-10
+    assert rel_inf(plan.matvec_adjoint(_dev(g), mfs.FP64).cpu().numpy(), ref_t) <= \
+        M.bar(rel_inf(M.matvec_T(pr, g, dt=F64), ref_t))
     out, info = plan.solve(_dev(net_flat(wl)), tol=1e-8)
     assert info["status"] == mfs.MFS_OK
     sol = pr.solve(wl.net[0], tol=1e-12)
-    assert rel_inf(out.cpu().numpy(), sol["out"]) <= M.solve_bars(pr, wl.net[0], 1e-8, sol, cap=1e-5)["out"]
+    bars = M.solve_bars(pr, wl.net[0], 1e-8, sol, cap=1e-5, gamma=info["gamma"].cpu().numpy())
+    assert bars["residual"] <= bars["residual_bound"]
+    assert rel_inf(out.cpu().numpy(), sol["out"]) <= bars["out"]
 
 
 @pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
@@ -86,13 +93,16 @@ def test_every_launch_shape(kind):
     pr = O.Problem.from_workload(wl)
     g = W.random_vector(pr.n_gamma, 76)
     ref, ref_t = pr.matvec(g), pr.matvec_T(g)
-    bar = M.bar(max(rel_inf(M.matvec(pr, g), ref), rel_inf(M.matvec_T(pr, g), ref_t)))
+
+    def bar(dt):
+        return M.bar(max(rel_inf(M.matvec(pr, g, dt=dt), ref), rel_inf(M.matvec_T(pr, g, dt=dt), ref_t)))
+    bars = {mfs.FP64: bar(F64), mfs.MIXED: bar(M.F32)}
     plan = mfs.Plan.from_workload(wl, mfs.MIXED)
     for tpl in (1, 2):
         for items in (1, 64, 16384):
             for per in (False, True):
                 plan.set_launch(tpl, items, per)
-                for prec, tol in ((mfs.FP64, 1e-10), (mfs.MIXED, bar)):
+                for prec, tol in bars.items():
                     e = (rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref),
                          rel_inf(plan.matvec_adjoint(_dev(g), prec).cpu().numpy(), ref_t))
                     assert max(e) <= tol, (tpl, items, per, prec, e)

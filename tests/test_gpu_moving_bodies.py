@@ -23,6 +23,8 @@ from tests._helpers import net_flat, rel_inf
 
 pytestmark = pytest.mark.gpu
 
+F64 = np.float64
+
 
 def _mfs():
     from paper_2409_04215_amd import mfs
@@ -51,8 +53,8 @@ def test_moved_plan_equals_new_plan(kind):
     ref_mv = pr_b.matvec(g)
     sol_b = pr_b.solve(b.net[0], tol=1e-12)
     ref_out = sol_b["out"]
-    mixed = (M.bar(rel_inf(M.matvec(pr_b, g), ref_mv)), M.solve_bars(pr_b, b.net[0], 1e-10, sol_b, cap=1e-5)["out"])
-    for prec, tol_mv, bar in ((mfs.FP64, 1e-10, 1e-8), (mfs.MIXED, *mixed)):
+    for prec, dt in ((mfs.FP64, F64), (mfs.MIXED, M.F32)):
+        tol_mv = M.bar(rel_inf(M.matvec(pr_b, g, dt=dt), ref_mv))
         moved = mfs.Plan.from_workload(a, prec)
         moved.solve(_dev(net_flat(a)), tol=1e-8)  # used at the old positions first
         moved.set_bodies(b.centre, b.rot)
@@ -65,7 +67,9 @@ def test_moved_plan_equals_new_plan(kind):
         out_f, info_f = fresh.solve(_dev(net_flat(b)), tol=1e-10)
         assert info_m["status"] == mfs.MFS_OK
         assert torch.equal(out_m, out_f) and list(info_m["iters"]) == list(info_f["iters"])
-        assert rel_inf(out_m.cpu().numpy(), ref_out) <= bar
+        bars = M.solve_bars(pr_b, b.net[0], 1e-10, sol_b, cap=1e-5, dt=dt, gamma=info_m["gamma"].cpu().numpy())
+        assert bars["residual"] <= bars["residual_bound"]
+        assert rel_inf(out_m.cpu().numpy(), ref_out) <= bars["out"]
         moved.close()
         fresh.close()
 
@@ -83,7 +87,6 @@ def test_moved_plan_graph_replay_and_bodies_of_several_shapes():
     pr_b = O.Problem.from_workload(b)
     sol_b = pr_b.solve(b.net[0], tol=1e-12)
     ref = sol_b["out"]
-    bar = M.solve_bars(pr_b, b.net[0], 1e-8, sol_b, cap=1e-5)["out"]
     moved = mfs.Plan.from_workload(a, mfs.MIXED)
     moved.set_graph(True)
     moved.solve(_dev(net_flat(a)), tol=1e-8)  # captures the matvec graph at the old positions
@@ -95,7 +98,9 @@ def test_moved_plan_graph_replay_and_bodies_of_several_shapes():
         out_f, _ = fresh.solve(_dev(net_flat(b)), tol=1e-8)
         assert info_m["status"] == mfs.MFS_OK
         assert torch.equal(out_m, out_f)
-        assert rel_inf(out_m.cpu().numpy(), ref) <= bar
+        bars = M.solve_bars(pr_b, b.net[0], 1e-8, sol_b, cap=1e-5, gamma=info_m["gamma"].cpu().numpy())
+        assert bars["residual"] <= bars["residual_bound"]
+        assert rel_inf(out_m.cpu().numpy(), ref) <= bars["out"]
     moved.close()
     fresh.close()
 
@@ -152,8 +157,10 @@ def test_moved_resistance_plan_equals_new_plan(kind):
     mfs = _mfs()
     a, b = _pair(kind, 4, 148)
     data = np.random.default_rng(149).standard_normal(4 * (6 if kind == W.STOKES else 1))
-    ref = O.ResistanceProblem.from_workload(b).solve(data.reshape(4, -1) if kind == W.STOKES else data,
-                                                     tol=1e-12)["out"]
+    rp = O.ResistanceProblem.from_workload(b)
+    rdata = data.reshape(4, -1) if kind == W.STOKES else data
+    r_sol = rp.solve(rdata, tol=1e-12)
+    ref = r_sol["out"]
     moved = mfs.Plan.from_workload(a, mfs.FP64, formulation=mfs.RESISTANCE)
     moved.solve(_dev(data), tol=1e-10)
     moved.set_bodies(b.centre, b.rot)
@@ -162,6 +169,8 @@ def test_moved_resistance_plan_equals_new_plan(kind):
     out_f, _ = fresh.solve(_dev(data), tol=1e-10)
     assert info_m["status"] == mfs.MFS_OK
     assert torch.equal(out_m, out_f)
-    assert rel_inf(out_m.cpu().numpy(), np.asarray(ref).reshape(-1)) <= 1e-8
+    bars = M.solve_bars(rp, rdata, 1e-10, r_sol, dt=F64, gamma=info_m["gamma"].cpu().numpy())
+    assert bars["residual"] <= bars["residual_bound"]
+    assert rel_inf(out_m.cpu().numpy(), np.asarray(ref).reshape(-1)) <= bars["out"]
     moved.close()
     fresh.close()
