@@ -153,3 +153,27 @@ def test_qr_resistance_plan(kind):
         print("resistance QR", kind, prec, "err", e, bars)
         assert info["status"] == mfs.MFS_OK and bars["residual"] <= bars["residual_bound"] and e <= bars["out"]
         plan.close()
+
+
+@pytest.mark.parametrize("kind,n_src,n_trg", [(W.LAPLACE, 10, 30), (W.STOKES, 10, 10), (W.STOKES, 11, 40),
+                                              (W.LAPLACE, 64, 64)])
+def test_qr_small_square_and_ragged_blocks(kind, n_src, n_trg):
+    """Blocks narrower than one 32-column panel (10 or 30 columns), square
+    blocks (M = N: S_L^+ is the inverse), and a width one column past whole
+    panels (33 = 32 + 1): pseudo-inverse apply and matvec of QR plans against
+    the oracle, within 4 x the model of a QR plan of the same precision."""
+    mfs = _mfs()
+    wl = W.small_cluster(3, kind, n_src, n_trg, seed=167, axes=(1.0, 1.0, 1.5))
+    pr = O.Problem.from_workload(wl)
+    g = W.random_vector(pr.n_gamma, 168)
+    ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
+    ref_A = pr.matvec(g)
+    for prec, dt in ((mfs.FP64, F64), (mfs.MIXED, M.F32)):
+        plan = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
+        e = (rel_inf(plan.precond_apply(_dev(g), 0, prec).cpu().numpy(), ref_p),
+             rel_inf(plan.matvec(_dev(g), prec).cpu().numpy(), ref_A))
+        bars = (M.bar(rel_inf(M.precond_apply(pr, g, qr=True, dt=dt), ref_p)),
+                M.bar(rel_inf(M.matvec(pr, g, qr=True, dt=dt), ref_A)))
+        print("QR", kind, n_src, n_trg, prec, "errors", e, "bars", bars)
+        assert e[0] <= bars[0] and e[1] <= bars[1]
+        plan.close()
