@@ -10,6 +10,7 @@ this script.  Calls only oracle/ and the seeded input generators.
     python tests/golden/make_golden.py rows_1000  # ellipsoids_1000: 2000 sampled rows, oracle and float32 model
     python tests/golden/make_golden.py batched    # batched_64: a stated subset of the 64 systems (~1.5 h)
     python tests/golden/make_golden.py e1000_laplace | e1000_stokes   # ellipsoids_1000 (~1 h / ~4 h)
+    python tests/golden/make_golden.py grad_200   # spheres_200: the adjoint gradients (~1 h)
 
 The long runs set MFS_ORACLE_NATIVE=1 (the oracle's C loops built with
 -O3 -march=native; same source) to fit in hours on 8 cores.
@@ -249,6 +250,67 @@ def rows_10000_model():
     _log("10^4 model rows stored")
 
 
+GRAD_SAMPLE = (0, 37, 74, 111, 148, 185)  # spheres_200 bodies whose model gradients are stored
+
+
+def _model_body_gradients(pr, info, bodies, dt):
+    """dJ/dc and dJ/d[f; t] of the listed bodies by the model of precision dt
+    (oracle/fp32_model.py): the pair sums that form them (all off-body pairs of
+    the body's points; the transposed all-pairs sum for the net gradient),
+    taken on the oracle's adjoint solution w and strengths sigma in `info`."""
+    w = info["w"].reshape(-1, 3)
+    sg = info["sol"]["sigma"].reshape(-1, 3)
+    cen = np.stack([b.centre for b in pr.bodies])
+    out_c, out_n = [], []
+    for k in bodies:
+        rt = pr.trg_body == k
+        rs = pr.src_body == k
+        gx, _ = M.pair_grad(pr.kind, pr.X[rt], pr.trg_body[rt], w[rt], pr.Y, pr.src_body, sg, cen, True, pr.mu, dt)
+        _, gy = M.pair_grad(pr.kind, pr.X, pr.trg_body, w, pr.Y[rs], pr.src_body[rs], sg[rs], cen, True, pr.mu, dt)
+        out_c.append(-(gx.sum(axis=0) + gy.sum(axis=0)))
+        t = -M.pair_sum(pr.kind, pr.Y[rs], pr.src_body[rs], pr.X, pr.trg_body, w, cen, False, pr.mu, dt).reshape(-1)
+        KN = O.K_matrix(pr.bodies[k].Y, pr.bodies[k].centre)
+        out_n.append(np.linalg.solve(KN.T @ KN, KN.T @ t))
+    return np.array(out_c), np.array(out_n)
+
+
+def grad_200():
+    """spheres_200 (200 unit spheres, N = 400, M = 800, Stokes mobility), J = sum |U|^2:
+    the oracle's dJ/dc and dJ/d[f; t] with both of its solves at GMRES tol 1e-13 (the
+    reference), 1e-12 and 1e-8, and the float32 and float64 models' gradients of the
+    bodies GRAD_SAMPLE on the reference's adjoint solution and strengths."""
+    t0 = time.time()
+    wl = W.spheres_200()
+    pr = O.Problem.from_workload(wl)
+    res = {}
+    for tol in (1e-13, 1e-12, 1e-8):
+        J, g, info = pr.velocity_loss_gradient(wl.net[0], tol=tol)
+        res[tol] = (J, g, info)
+        _log(f"spheres_200 gradient at tol {tol:g}: J = {J:.16e}, {info['sol']['iters']} + {info['adj_iters']} "
+             f"iterations, {time.time() - t0:.0f} s")
+    cols = []
+    for tol in (1e-13, 1e-12, 1e-8):
+        cols += [res[tol][1], np.asarray(res[tol][2]["grad_net"]).reshape(-1, 6)]
+    hdr = (f"the seeded spheres_200 workload (200 unit spheres, N = 400, M = 800, Stokes mobility), "
+           f"J = sum |U|^2 = {res[1e-13][0]:.17e}:\n"
+           f"per body dJ/dc (3) and dJ/d[f; t] (6) by the FP64 oracle with both solves at GMRES tol 1e-13, "
+           f"then at 1e-12, then at 1e-8; {time.time() - t0:.0f} s.\n"
+           f"Written by tests/golden/make_golden.py grad_200 (oracle only).")
+    np.savetxt(os.path.join(HERE, "spheres_200_gradient.txt"), np.concatenate(cols, axis=1), fmt="%.17e", header=hdr)
+    info = res[1e-13][2]
+    mc32, mn32 = _model_body_gradients(pr, info, GRAD_SAMPLE, M.F32)
+    _log(f"spheres_200 float32 model gradients, {time.time() - t0:.0f} s")
+    mc64, mn64 = _model_body_gradients(pr, info, GRAD_SAMPLE, np.float64)
+    _log(f"spheres_200 float64 model gradients, {time.time() - t0:.0f} s")
+    tab = np.concatenate([np.array(GRAD_SAMPLE, np.float64)[:, None], mc32, mn32, mc64, mn64], axis=1)
+    hdr = ("the float32 and float64 models (oracle/fp32_model.py) of the spheres_200 gradients of the bodies in the "
+           "first column, on the oracle's tol-1e-13 adjoint solution and strengths:\n"
+           "columns: body, dJ/dc (3) and dJ/d[f; t] (6) by the float32 model, then the same by the float64 model.\n"
+           f"Written by tests/golden/make_golden.py grad_200 (oracle/ only).")
+    np.savetxt(os.path.join(HERE, "spheres_200_gradient_model.txt"), tab, fmt="%.17e", header=hdr)
+    _log("spheres_200 gradients stored")
+
+
 def _model64_rows(pr, wl, rows, g, sm):
     """Right-hand side and both matvecs on `rows` by the float64 model
     (oracle/fp32_model.py with dt = float64: another summation order and an
@@ -290,7 +352,7 @@ def rows_10000_model64():
     _log("10^4 float64 model rows stored")
 
 
-JOBS = {"e100_tight": e100_tight, "rows_1000_model64": rows_1000_model64, "rows_10000_model64": rows_10000_model64, "rows_1000": rows_1000, "rows_10000_model": rows_10000_model, "two_way": two_way, "rows_10000": rows_10000, "batched": batched,
+JOBS = {"grad_200": grad_200, "e100_tight": e100_tight, "rows_1000_model64": rows_1000_model64, "rows_10000_model64": rows_10000_model64, "rows_1000": rows_1000, "rows_10000_model": rows_10000_model, "two_way": two_way, "rows_10000": rows_10000, "batched": batched,
         "e1000_laplace": lambda: e1000(W.LAPLACE), "e1000_stokes": lambda: e1000(W.STOKES)}
 
 

@@ -178,3 +178,45 @@ def test_elastance_gradient_matches_oracle():
         print("elastance", prec, "J", J, J_ref, "grad err", e, "adjoint iters", iters)
         assert abs(J - J_ref) <= 1e-6 * J_ref and e <= bar
         plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_gradient_spheres_200_vs_stored_oracle():
+    """Full size (200 unit spheres, N = 400, M = 800): dJ/dc and dJ/d[f; t] of
+    J = sum |U|^2 against the oracle's, stored by tests/golden/make_golden.py
+    grad_200 with both oracle solves at tol 1e-13.  FP64 plan at tol 1e-12 and
+    mixed at tol 1e-8; bars 4 x (the model's error of the gradient on the
+    stored sample of bodies, on the oracle's adjoint solution and strengths +
+    the oracle's own error at the plan's tol, also stored), at most 1e-5."""
+    import os
+    mfs = _mfs()
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    path, path_m = os.path.join(golden, "spheres_200_gradient.txt"), os.path.join(golden, "spheres_200_gradient_model.txt")
+    if not (os.path.exists(path) and os.path.exists(path_m)):
+        pytest.skip("spheres_200 gradients not written yet (tests/golden/make_golden.py grad_200)")
+    tab, mod = np.loadtxt(path), np.loadtxt(path_m)
+    g_ref, n_ref = tab[:, 0:3], tab[:, 3:9]
+    at_tol = {1e-12: (tab[:, 9:12], tab[:, 12:18]), 1e-8: (tab[:, 18:21], tab[:, 21:27])}
+    bodies = mod[:, 0].astype(int)
+    model = {mfs.MIXED: (mod[:, 1:4], mod[:, 4:10]), mfs.FP64: (mod[:, 10:13], mod[:, 13:19])}
+
+    def rel(a, r):
+        return float(np.abs(np.asarray(a) - r).max() / np.abs(r).max())
+
+    def rel_rows(a, r):  # the sampled rows, against the largest entry over all bodies
+        return float(np.abs(a - r[bodies]).max() / np.abs(r).max())
+    wl = W.spheres_200()
+    for prec, tol in ((mfs.FP64, 1e-12), (mfs.MIXED, 1e-8)):
+        (gt, nt), (mc, mn) = at_tol[tol], model[prec]
+        bar_c = min(1e-5, M.bar(rel_rows(mc, g_ref) + rel(gt, g_ref)))
+        bar_n = min(1e-5, M.bar(rel_rows(mn, n_ref) + rel(nt, n_ref)))
+        plan = mfs.Plan.from_workload(wl, prec)
+        out, info = plan.solve(_dev(net_flat(wl)), tol=tol)
+        gc, gn, iters, _, st = plan.gmres_solve_backward(info["gamma"], info["s0"], 2.0 * out, tol=tol,
+                                                         want_net=True)
+        assert info["status"] == mfs.MFS_OK and st == mfs.MFS_OK
+        e = (rel(gc.cpu().numpy().reshape(-1, 3), g_ref), rel(gn.cpu().numpy().reshape(-1, 6), n_ref))
+        print(f"spheres_200 prec={prec} tol={tol:g}: dJ/dc err {e[0]:.2e} (bar {bar_c:.2e}), "
+              f"dJ/dnet err {e[1]:.2e} (bar {bar_n:.2e}), adjoint iters {iters}", flush=True)
+        assert e[0] <= bar_c and e[1] <= bar_n
+        plan.close()
