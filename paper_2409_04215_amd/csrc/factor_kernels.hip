@@ -52,12 +52,6 @@ __device__ double block_sum_fixed(double x, double *sh) {
     return t;
 }
 
-// sum over the wave, the same value in every lane
-__device__ __forceinline__ double wave_sum(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    return __shfl(x, 0, 64);
-}
-
 // One panel (columns k0 .. k0+kb-1, rows k0 .. m-1) of every matrix; T of the panel to
 // Tp[b][NB][NB] (row-major, zero outside the leading kb x kb upper triangle).
 // Step j (column c = k0 + j): the norm of the column below the diagonal (all threads,
