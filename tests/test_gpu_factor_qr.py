@@ -177,3 +177,26 @@ def test_qr_small_square_and_ragged_blocks(kind, n_src, n_trg):
         print("QR", kind, n_src, n_trg, prec, "errors", e, "bars", bars)
         assert e[0] <= bars[0] and e[1] <= bars[1]
         plan.close()
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+def test_qr_adjoint_matvec_and_transpose_blocks(kind):
+    """The transposed blocks of a QR plan ((S_L^+)^T = Q R^-T: R^-T in FP64, then Q
+    in FP32 for mixed plans) in the adjoint matvec and in precond_apply, against
+    the oracle within 4 x the QR model of each precision."""
+    mfs = _mfs()
+    wl = W.small_cluster(4, kind, 45, 301, seed=169)
+    pr = O.Problem.from_workload(wl)
+    w = W.random_vector(pr.n_gamma, 170)
+    v = W.random_vector(pr.n_lambda, 171)
+    ref_t = pr.matvec_T(w)
+    ref_p = np.concatenate([pr.pinv_apply_T(k, pr.sblock(v, k)) for k in range(wl.n_body)])
+    for prec, dt in ((mfs.FP64, F64), (mfs.MIXED, M.F32)):
+        plan = mfs.Plan.from_workload(wl, prec, factorization=mfs.FACTOR_QR)
+        e = (rel_inf(plan.matvec_adjoint(_dev(w), prec).cpu().numpy(), ref_t),
+             rel_inf(plan.precond_apply(_dev(v), mfs.TRANSPOSE, prec).cpu().numpy(), ref_p))
+        bars = (M.bar(rel_inf(M.matvec_T(pr, w, qr=True, dt=dt), ref_t)),
+                M.bar(rel_inf(M.precond_apply(pr, v, transpose=True, qr=True, dt=dt), ref_p)))
+        print("QR adjoint", kind, prec, "errors", e, "bars", bars)
+        assert e[0] <= bars[0] and e[1] <= bars[1]
+        plan.close()
