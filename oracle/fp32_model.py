@@ -362,8 +362,8 @@ def solve_bars(pr, net, tol, ref=None, keys=("out",), cap=None, qr=False, dt=F32
       gamma + delta, delta = (A_model - A) gamma the model's matvec error at
       the solution, so the outputs are known only up to what delta does to
       them through the recovery (S_L^+ with FP64 factors, eqs. (vkal),
-      (getU); for dt = float64 the model's own FP64 factors, which differ
-      from the oracle's as a second FP64 factorisation does): this limit is
+      (getU); for dt = float64 the model's own backward-stable FP64
+      factors, which differ from the oracle's as the path's do): this limit is
       the change of each output under gamma + delta.
     stop: the plan's stopping factor (mfs_plan_set_stop_factor; STOP unless
     the plan sets another).
