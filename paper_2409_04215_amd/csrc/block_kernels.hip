@@ -47,12 +47,17 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 //    k = 16 (l/32) + t, t < 16, one MFMA per t;
 //  * f64, v_mfma_f64_16x16x4f64 (2 x 2 blocks of 16 x 16): lane l holds
 //    A[l%16][k] and B[k][l%16] for k = 4 (l/16) + t, t < 4.
+// A group's last column tile, when it holds at most GEMM_NARROW columns, is
+// staged the same way but summed on the VALU (lane l: row l%32, columns
+// l/32 + 2j), so the matrix cores do no work on padding columns there.
 // Tiles are handed out XCD-aware: workgroup b runs on XCD b % 8 and takes
 // tile (b % 8) * per_xcd + b / 8, so the column tiles of one (row tile, K
 // range), which are consecutive in the tile list, run on one XCD and fetch
 // their shared rows of A into its L2 once.  A K range is split over several
 // tiles when there are few output tiles; split slices land in a partial
-// buffer that a second kernel sums in a fixed order.
+// buffer that a second kernel sums in a fixed order.  (Summing them in the
+// kernel, by the slice that arrives last at a per-tile counter, needs an
+// agent-scope release per workgroup: it measured 57 us against 15 + 5 us.)
 // ---------------------------------------------------------------------------
 constexpr int RUN_BYTES = 128;                      // one K run per LDS stage
 constexpr int ROW_BYTES = RUN_BYTES + 16;           // padded LDS row
@@ -159,7 +164,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
         }
     };
 
+    // narrow tile: lane l sums row l%32 against columns l/32 + 2j, j < 4, of the staged run
+    T nacc[4] = {T(0), T(0), T(0), T(0)};
+    auto narrow_run = [&]() {
+        const T *ar = As + (lane & 31) * LD;
+#pragma unroll 1
+        for (int kk = 0; kk < KR; kk += E) {
+            const Piece<T> x = *reinterpret_cast<const Piece<T> *>(ar + kk);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const Piece<T> y = *reinterpret_cast<const Piece<T> *>(Bs + ((lane >> 5) + 2 * j) * LD + kk);
+#pragma unroll
+                for (int e = 0; e < E; ++e) nacc[j] += x.v[e] * y.v[e];
+            }
+        }
+    };
+
     T val[16];
+    const bool narrow = tl.narrow != 0;
     if (kb < ke) fetch(kb);
     if constexpr (sizeof(T) == 4) {
         const int c = lane & 31, h = lane >> 5;
@@ -168,6 +190,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
             stage();
             wave_lds_sync();
             if (k0 + KR < ke) fetch(k0 + KR);
+            if (narrow) {
+                narrow_run();
+                wave_lds_sync();  // the next run's stores follow these reads
+                continue;
+            }
             float av[16], bv[16];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -189,6 +216,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
             stage();
             wave_lds_sync();
             if (k0 + KR < ke) fetch(k0 + KR);
+            if (narrow) {
+                narrow_run();
+                wave_lds_sync();
+                continue;
+            }
             double av[2][4], bv[2][4];
 #pragma unroll
             for (int u = 0; u < 2; ++u)
@@ -215,6 +247,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
 #pragma unroll
                 for (int r = 0; r < 4; ++r) val[(2 * u + w) * 4 + r] = acc[u][w][r];
     }
+    if (narrow)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) val[r] = r < 4 ? nacc[r & 3] : T(0);
     // partial tiles of waves 1-3 through their own stages, added to wave 0's in wave order
     T *red = reinterpret_cast<T *>(smem[wave]);
     if (wave > 0)
@@ -228,35 +263,38 @@ __global__ __launch_bounds__(256) void gemm_kernel(int n_tiles, int per_xcd, con
 #pragma unroll
         for (int r = 0; r < 16; ++r) val[r] += o[r * 64 + lane];
     }
-    if constexpr (sizeof(T) == 4) {
-        // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
-        const int col = tl.n0 + (lane & 31);
-        if (col < g.ncol) {
-            T *out = partial ? partial + tl.split * part_split_stride + (int64_t)(g.col_begin + col) * part_col_stride
-                             : C + c_col_off[g.col_begin + col];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = tl.m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                if (row < g.M) out[row] = val[r];
-            }
+    // output element of value slot r of this lane; false outside the group's matrix
+    auto slot = [&](int r, int &row, int &col) -> bool {
+        if (tl.narrow) {
+            row = tl.m0 + (lane & 31);
+            col = tl.n0 + (lane >> 5) + 2 * r;
+            if (r >= 4) return false;
+        } else if constexpr (sizeof(T) == 4) {
+            // D layout (32x32x2): lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, col l%32
+            row = tl.m0 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+            col = tl.n0 + (lane & 31);
+        } else {
+            // D layout (16x16x4 f64, measured on gfx950): lane l, reg r -> row l/16 + 4 r, col l%16;
+            // slot (2 u + w) * 4 + r holds block (u, w)
+            const int bl = r / 4;
+            row = tl.m0 + 16 * (bl >> 1) + (lane >> 4) + 4 * (r % 4);
+            col = tl.n0 + 16 * (bl & 1) + (lane & 15);
         }
-    } else {
-        // D layout (16x16x4 f64, measured on gfx950): lane l, reg r -> row l/16 + 4 r, col l%16
-        const int q = lane >> 4, c16 = lane & 15;
+        return row < g.M && col < g.ncol;
+    };
+    if (!partial) {
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const int col = tl.n0 + 16 * w + c16;
-            if (col >= g.ncol) continue;
-            T *out = partial ? partial + tl.split * part_split_stride + (int64_t)(g.col_begin + col) * part_col_stride
-                             : C + c_col_off[g.col_begin + col];
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = tl.m0 + 16 * u + q + 4 * r;
-                    if (row < g.M) out[row] = val[(2 * u + w) * 4 + r];
-                }
+        for (int r = 0; r < 16; ++r) {
+            int row, col;
+            if (slot(r, row, col)) C[c_col_off[g.col_begin + col] + row] = val[r];
         }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int row, col;
+        if (slot(r, row, col))
+            partial[tl.split * part_split_stride + (int64_t)(g.col_begin + col) * part_col_stride + row] = val[r];
     }
 }
 

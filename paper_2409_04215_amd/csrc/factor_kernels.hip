@@ -6,7 +6,7 @@
 // Section 2.3, applied in the same two steps (Q^T, then R^-1).
 //
 // Blocked Householder QR (compact WY form).  The columns are taken in panels
-// of NB = 32; the reflectors H_j = I - tau_j v_j v_j^T of one panel (v_j[j] = 1,
+// of NB = 16; the reflectors H_j = I - tau_j v_j v_j^T of one panel (v_j[j] = 1,
 // stored below the diagonal of column j, R on and above it) multiply to
 // H_k0 ... H_k0+kb-1 = I - V T V^T with T kb x kb upper triangular:
 //   * panel_qr_kernel: one workgroup per matrix factors the panel column by
@@ -32,8 +32,13 @@ namespace mfs {
 namespace {
 
 constexpr int FB = 256;   // threads per workgroup (inverse, ratio, WY update)
-constexpr int NB = 32;    // panel width
-constexpr int PT = 1024;  // threads of the panel kernel
+// Panel width.  16 columns made the QR of a 2400 x 1200 block faster than 32
+// (panels 20.6 ms + updates 10.4 ms against 33 ms + 7.6 ms): the one-workgroup
+// panel factorisation does half the work per column and the MFMA updates take
+// the rest.  The kernels also build for NB = 32.
+constexpr int NB = 16;
+static_assert(NB == 16 || NB == 32, "the WY update's MFMA tiles cover 16 or 32 panel columns");
+constexpr int PT = 32 * NB;  // threads of the panel kernel: half a wave per panel column
 constexpr int PW = PT / 64;
 constexpr int CT = 16;    // columns per workgroup of the WY update
 
@@ -153,7 +158,8 @@ __device__ __forceinline__ double panel_v(const double *__restrict__ v, int lda,
 // op(T) = T^T (TRANS: the QR's trailing update) or T (accumulating Q).
 // Grid (column tiles of CT, batch); four waves.
 //  1. P = V^T C (NB x CT): each wave sums a quarter of the rows in steps of 16;
-//     MFMA A = V^T (lane l: V[r][k0 + l%16 (+16)]), B = C (lane l: C[r][col l%16]),
+//     MFMA A = V^T (lane l: V[r][k0 + l%16], and V[r][k0 + 16 + l%16] in a second
+//     accumulator when NB = 32), B = C (lane l: C[r][col l%16]),
 //     the k slot l/16 of MFMA t standing for row r = r0 + 4 (l/16) + t in both;
 //     D layout (16x16x4 f64): lane l, reg q -> row l/16 + 4 q, col l%16.
 //  2. The four partial P added in wave order, W = op(T) P in LDS.
@@ -191,18 +197,18 @@ __global__ __launch_bounds__(FB) void wy_apply_kernel(const double *__restrict__
             const int r = rb + u;
             cv[u] = (cok && r < m) ? ccol[r] : 0.0;
             va[u] = panel_v(v, lda, m, k0, kb, r, c16);
-            vb[u] = panel_v(v, lda, m, k0, kb, r, 16 + c16);
+            if constexpr (NB == 32) vb[u] = panel_v(v, lda, m, k0, kb, r, 16 + c16);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], cv[u], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[u], cv[u], acc1, 0, 0, 0);
+            if constexpr (NB == 32) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[u], cv[u], acc1, 0, 0, 0);
         }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         Pw[wave][q + 4 * r][c16] = acc0[r];
-        Pw[wave][16 + q + 4 * r][c16] = acc1[r];
+        if constexpr (NB == 32) Pw[wave][16 + q + 4 * r][c16] = acc1[r];
     }
     __syncthreads();
     // 2. P summed over the waves in order, W = op(T) P

@@ -660,7 +660,8 @@ void rotate_gram(const double *G0i, const double *R, double *Gi) {
 // Work tables of one grouped GEMM: tiles of 32 x 32 outputs (one workgroup of
 // four waves each), K split into n_split ranges of at least 512 when there are
 // fewer than 1024 tiles (the fastest of the settings timed at 100 and 1000
-// bodies).
+// bodies).  A group's last column tile is narrow (VALU) when it holds at most
+// GEMM_NARROW columns, so that no matrix-core work goes to padding columns there.
 int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &groups,
                       const std::vector<int32_t> &col_group, const std::vector<int64_t> &b_col_off, hipStream_t s) {
     int64_t tiles32 = 0, kmax = 0, mmax = 0;
@@ -681,7 +682,8 @@ int build_gemm_launch(mfs_plan_s::GemmTables &T, const std::vector<GemmGroup> &g
             for (int sp = 0; sp < n_split; ++sp)
                 for (int n0 = 0; n0 < g.ncol; n0 += 32) {
                     const int k0 = std::min(g.K, sp * kchunk), k1 = std::min(g.K, k0 + kchunk);
-                    tiles.push_back(GemmTile{(int32_t)gi, m0, n0, k0, k1, sp});
+                    const int32_t narrow = g.ncol - n0 <= GEMM_NARROW ? 1 : 0;
+                    tiles.push_back(GemmTile{(int32_t)gi, m0, n0, k0, k1, sp, narrow});
                 }
     }
     MFS_TRY(upload_vec(T.groups, groups, s));

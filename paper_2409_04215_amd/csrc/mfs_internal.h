@@ -181,7 +181,11 @@ int launch_residual(int64_t n, const int32_t *body, const int32_t *kind, const i
 // ---------------------------------------------------------------------------
 // Block (one-body) kernels (block_kernels.hip)
 // ---------------------------------------------------------------------------
-struct GemmTile { int32_t group, m0, n0, k0, k1, split; };
+// One workgroup's task: output tile (m0, n0) of a group over K range [k0, k1), split slice
+// `split`; `narrow`: the tile has at most GEMM_NARROW columns and is summed on the VALU
+// instead of the matrix cores.
+struct GemmTile { int32_t group, m0, n0, k0, k1, split, narrow; };
+constexpr int GEMM_NARROW = 8;
 struct GemmGroup {
     int32_t M, K;             // A is M x K row-major (lda = K)
     int32_t col_begin, ncol;  // columns [col_begin, col_begin+ncol) of the column table
