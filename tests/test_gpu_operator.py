@@ -99,6 +99,33 @@ def test_precond_apply(kind):
 
 
 @pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
+@pytest.mark.parametrize("n_body", [1, 8, 9, 33, 40])
+def test_precond_apply_column_tiles(kind, n_body):
+    """The pseudo-inverse blocks at body counts that end the grouped GEMM's
+    column tiles every way: a lone narrow tile summed on the VALU (1 and 8
+    columns), a matrix-core tile with padding columns (9), whole tiles followed
+    by a narrow one (33, 40); K = 3M = 600 (Stokes) is split over two slices."""
+    mfs = _mfs()
+    wl = W.small_cluster(n_body, kind, 30, 200, seed=50 + n_body)
+    pr = O.Problem.from_workload(wl)
+    plan = _plan(wl, mfs.MIXED)
+    g = W.random_vector(pr.n_gamma, 61)
+    v = W.random_vector(pr.n_lambda, 62)
+    ref_p = np.concatenate([pr.pinv_apply(k, pr.gblock(g, k)) for k in range(wl.n_body)])
+    ref_t = np.concatenate([pr.pinv_apply_T(k, pr.sblock(v, k)) for k in range(wl.n_body)])
+
+    def bar(dt):
+        return M.bar(max(rel_inf(M.precond_apply(pr, g, dt=dt), ref_p),
+                         rel_inf(M.precond_apply(pr, v, transpose=True, dt=dt), ref_t)))
+    for prec, tol in ((mfs.FP64, bar(F64)), (mfs.MIXED, bar(M.F32))):
+        got = plan.precond_apply(_dev(g), 0, prec).cpu().numpy()
+        got_t = plan.precond_apply(_dev(v), mfs.TRANSPOSE, prec).cpu().numpy()
+        e = (rel_inf(got, ref_p), rel_inf(got_t, ref_t))
+        print(kind, n_body, prec, e, tol)
+        assert max(e) <= tol, (prec, e, tol)
+
+
+@pytest.mark.parametrize("kind", [W.STOKES, W.LAPLACE])
 def test_matvec_and_adjoint(kind):
     mfs = _mfs()
     wl, pr = _case(kind)
