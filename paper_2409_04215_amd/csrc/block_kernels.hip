@@ -414,25 +414,45 @@ __device__ __forceinline__ void write_src(void *srcS, void *srcL, int prec, int 
 // Projection of one body's strength vector, world frame, FP64.
 // mode: 0 = (I - L) v ; also used to read the 6-vector / mean.
 // Stokes: w = K_N^T v = [sum v_j; sum d_j x v_j]; z = G^{-1} w; out_j = v_j - (z_v + z_w x d_j)
+// With n_slices > 1, lam is not read: the values are the sums of the split slices of
+// the GEMM that produced them (in slice order, as gemm_reduce_kernel adds them).
 template <class T>
 __global__ __launch_bounds__(256) void project_kernel(BodyView bv, const T *__restrict__ lam, int rotate, int project,
                                                       double *__restrict__ out64, void *__restrict__ srcS,
-                                                      void *__restrict__ srcL, int src_prec) {
+                                                      void *__restrict__ srcL, int src_prec,
+                                                      const T *__restrict__ part, int n_slices, int64_t split_stride,
+                                                      int64_t col_stride, const int32_t *__restrict__ col_of_body) {
     __shared__ double sh[4][6];
     const int64_t b = blockIdx.x;
     const int kind = bv.kind[b];
     const int n = bv.n_src[b];
     const int64_t off = bv.lam_off[b];
     const int64_t row0 = bv.src_row[b];
+    const T *pb = n_slices > 1 ? part + (int64_t)col_of_body[b] * col_stride : nullptr;
+    auto val = [&](int64_t j) -> double {
+        if (n_slices <= 1) return (double)lam[off + j];
+        T s = T(0);
+        for (int sp = 0; sp < n_slices; ++sp) s += pb[sp * split_stride + j];
+        return (double)s;
+    };
+    // the projection reads every value twice; the first pass keeps them here (each
+    // thread reads back only its own entries)
+    constexpr int CACHE = 2048;
+    __shared__ double cache[CACHE];
+    const bool cached = project && (kind == MFS_LAPLACE ? n : 3 * n) <= CACHE;
     if (kind == MFS_LAPLACE) {
         double s[1] = {0.0};
         if (project) {
-            for (int j = threadIdx.x; j < n; j += blockDim.x) s[0] += (double)lam[off + j];
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                const double v = val(j);
+                if (cached) cache[j] = v;
+                s[0] += v;
+            }
             block_sum<1>(s, reinterpret_cast<double(*)[1]>(sh));
         }
         const double mean = project ? s[0] / n : 0.0;
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            const double v = (double)lam[off + j] - mean;
+            const double v = (cached ? cache[j] : val(j)) - mean;
             if (out64) out64[off + j] = v;
             write_src(srcS, srcL, src_prec, kind, row0 + j, &v);
         }
@@ -444,7 +464,12 @@ __global__ __launch_bounds__(256) void project_kernel(BodyView bv, const T *__re
     if (project) {
         double w[6] = {0, 0, 0, 0, 0, 0};
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            double v[3] = {(double)lam[off + 3 * j], (double)lam[off + 3 * j + 1], (double)lam[off + 3 * j + 2]};
+            double v[3] = {val(3 * j), val(3 * j + 1), val(3 * j + 2)};
+            if (cached) {
+                cache[3 * j] = v[0];
+                cache[3 * j + 1] = v[1];
+                cache[3 * j + 2] = v[2];
+            }
             double vw[3];
             if (rotate) rot_apply(R, v, false, vw);
             else { vw[0] = v[0]; vw[1] = v[1]; vw[2] = v[2]; }
@@ -463,7 +488,16 @@ __global__ __launch_bounds__(256) void project_kernel(BodyView bv, const T *__re
         }
     }
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        double v[3] = {(double)lam[off + 3 * j], (double)lam[off + 3 * j + 1], (double)lam[off + 3 * j + 2]};
+        double v[3];
+        if (cached) {
+            v[0] = cache[3 * j];
+            v[1] = cache[3 * j + 1];
+            v[2] = cache[3 * j + 2];
+        } else {
+            v[0] = val(3 * j);
+            v[1] = val(3 * j + 1);
+            v[2] = val(3 * j + 2);
+        }
         double vw[3];
         if (rotate) rot_apply(R, v, false, vw);
         else { vw[0] = v[0]; vw[1] = v[1]; vw[2] = v[2]; }
@@ -803,14 +837,14 @@ __global__ void make_factor_kernel(int rows, int cols, const double *__restrict_
 // host launchers
 // ---------------------------------------------------------------------------
 int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, const int64_t *b_col_off, float *C,
-                    const int64_t *c_col_off, float *partial, hipStream_t s) {
+                    const int64_t *c_col_off, float *partial, hipStream_t s, bool sum_slices) {
     if (G.n_tiles == 0) return MFS_OK;
     float *part = G.n_split > 1 ? partial : nullptr;
     const int per_xcd = (G.n_tiles + 7) / 8;
     gemm_kernel<float><<<8 * per_xcd, 256, 0, s>>>(G.n_tiles, per_xcd, G.tiles, G.groups, Apool, B, b_col_off, C,
                                                           c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
-    if (part) {
+    if (part && sum_slices) {
         gemm_reduce_kernel<float><<<dim3(G.n_cols, (unsigned)((G.part_col_stride + 255) / 256)), 256, 0, s>>>(
             G.col_group, G.groups, part, G.part_col_stride, G.part_split_stride, G.n_split, C, c_col_off);
         MFS_HIP_TRY(hipGetLastError());
@@ -819,14 +853,14 @@ int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, con
 }
 
 int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, const int64_t *b_col_off, double *C,
-                    const int64_t *c_col_off, double *partial, hipStream_t s) {
+                    const int64_t *c_col_off, double *partial, hipStream_t s, bool sum_slices) {
     if (G.n_tiles == 0) return MFS_OK;
     double *part = G.n_split > 1 ? partial : nullptr;
     const int per_xcd = (G.n_tiles + 7) / 8;
     gemm_kernel<double><<<8 * per_xcd, 256, 0, s>>>(G.n_tiles, per_xcd, G.tiles, G.groups, Apool, B, b_col_off, C,
                                                             c_col_off, part, G.part_col_stride, G.part_split_stride, G.vec4);
     MFS_HIP_TRY(hipGetLastError());
-    if (part) {
+    if (part && sum_slices) {
         gemm_reduce_kernel<double><<<dim3(G.n_cols, (unsigned)((G.part_col_stride + 255) / 256)), 256, 0, s>>>(
             G.col_group, G.groups, part, G.part_col_stride, G.part_split_stride, G.n_split, C, c_col_off);
         MFS_HIP_TRY(hipGetLastError());
@@ -866,14 +900,18 @@ int launch_cast(int64_t n, const void *in, bool in_f32, void *out, hipStream_t s
 }
 
 int launch_project(const BodyView &bv, const void *lam, bool lam_f32, bool rotate, bool project, double *out64,
-                   void *srcS, void *srcL, int src_prec, hipStream_t s) {
+                   void *srcS, void *srcL, int src_prec, hipStream_t s, const SplitSlices *slices) {
     if (bv.n_body == 0) return MFS_OK;
+    const SplitSlices none;
+    const SplitSlices &sl = slices && slices->n > 1 ? *slices : none;
     if (lam_f32)
-        project_kernel<float><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const float *)lam, rotate, project, out64,
-                                                                  srcS, srcL, src_prec);
+        project_kernel<float><<<(unsigned)bv.n_body, 256, 0, s>>>(
+            bv, (const float *)lam, rotate, project, out64, srcS, srcL, src_prec, (const float *)sl.part, sl.n,
+            sl.split_stride, sl.col_stride, sl.col_of_body);
     else
-        project_kernel<double><<<(unsigned)bv.n_body, 256, 0, s>>>(bv, (const double *)lam, rotate, project, out64,
-                                                                   srcS, srcL, src_prec);
+        project_kernel<double><<<(unsigned)bv.n_body, 256, 0, s>>>(
+            bv, (const double *)lam, rotate, project, out64, srcS, srcL, src_prec, (const double *)sl.part, sl.n,
+            sl.split_stride, sl.col_stride, sl.col_of_body);
     MFS_HIP_TRY(hipGetLastError());
     return MFS_OK;
 }

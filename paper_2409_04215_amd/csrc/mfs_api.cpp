@@ -474,7 +474,7 @@ struct mfs_plan_s {
     // factors
     DevBuf A32, A64;
     std::vector<Factor> factors;
-    DevBuf d_col_gam, d_col_lam;
+    DevBuf d_col_gam, d_col_lam, d_col_of_body;
     // grouped GEMMs: forward U^T then W; transposed W^T then U
     struct GemmTables {
         DevBuf groups, tiles, col_group;
@@ -725,8 +725,15 @@ int build_gemm_tables(mfs_plan p, hipStream_t s) {
         t1.push_back(GemmGroup{F.dN, F.dN, cb, nc, F.wt_off});
         t2.push_back(GemmGroup{F.dM, F.dN, cb, nc, F.u_off});
     }
+    std::vector<int32_t> col_of_body(std::max<int64_t>(1, p->n_body), 0);
+    {
+        int32_t c = 0;
+        for (auto &cf : cols)
+            for (int32_t b : cf) col_of_body[b] = c++;
+    }
     MFS_TRY(upload_vec(p->d_col_gam, col_gam, s));
     MFS_TRY(upload_vec(p->d_col_lam, col_lam, s));
+    MFS_TRY(upload_vec(p->d_col_of_body, col_of_body, s));
     MFS_TRY(build_gemm_launch(p->gm[0], g1, col_group, col_gam, s));
     MFS_TRY(build_gemm_launch(p->gm[1], g2, col_group, col_lam, s));
     MFS_TRY(build_gemm_launch(p->gm[2], t1, col_group, col_lam, s));
@@ -1385,30 +1392,42 @@ namespace {
 // its entries are large and cancel on smooth inputs, so an FP32 copy errs at the solution
 // by about 2e-5 of the operator's output against 6e-7 for the SVD's W = V Sigma^+ (a Type
 // T block, cond 5.4e6), which costs refinement rounds; it is applied in FP64 instead.
+// The second GEMM's split-K slices are added by the projection kernel, the one reader
+// of its output, in the order its own reduction would add them (one launch fewer).
 int precond_fwd(mfs_plan p, const double *in, int prec, bool project, double *out64, int src_prec, hipStream_t s) {
     BodyView bv = p->view();
     bool f32 = prec == MFS_MIXED;
+    const GemmLaunch &G2 = p->gm[1].L;
+    SplitSlices sl;
+    sl.n = G2.n_split;
+    sl.split_stride = G2.part_split_stride;
+    sl.col_stride = G2.part_col_stride;
+    sl.col_of_body = p->d_col_of_body.as<int32_t>();
     if (f32) {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g32.ptr, true, false, s));
         MFS_TRY(launch_gemm_f32(p->gm[0].L, p->A32.as<float>(), p->ws_g32.as<float>(), p->d_col_gam.as<int64_t>(),
                                 p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s));
         if (p->factorization == MFS_FACTOR_QR) {
             MFS_TRY(launch_cast(p->n_lambda, p->ws_l32a.ptr, true, p->ws_l64a.ptr, s));
-            MFS_TRY(launch_gemm_f64(p->gm[1].L, p->A64.as<double>(), p->ws_l64a.as<double>(),
-                                    p->d_col_lam.as<int64_t>(), p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(),
-                                    p->gpart64.as<double>(), s));
+            MFS_TRY(launch_gemm_f64(G2, p->A64.as<double>(), p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(),
+                                    p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s,
+                                    false));
+            sl.part = p->gpart64.ptr;
             f32 = false;  // lambda in FP64
         } else {
-            MFS_TRY(launch_gemm_f32(p->gm[1].L, p->A32.as<float>(), p->ws_l32a.as<float>(),
-                                    p->d_col_lam.as<int64_t>(), p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(),
-                                    p->gpart32.as<float>(), s));
+            MFS_TRY(launch_gemm_f32(G2, p->A32.as<float>(), p->ws_l32a.as<float>(), p->d_col_lam.as<int64_t>(),
+                                    p->ws_l32b.as<float>(), p->d_col_lam.as<int64_t>(), p->gpart32.as<float>(), s,
+                                    false));
+            sl.part = p->gpart32.ptr;
         }
     } else {
         MFS_TRY(launch_rotate_in(bv, in, p->ws_g64.ptr, false, false, s));
         MFS_TRY(launch_gemm_f64(p->gm[0].L, p->A64.as<double>(), p->ws_g64.as<double>(), p->d_col_gam.as<int64_t>(),
                                 p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s));
-        MFS_TRY(launch_gemm_f64(p->gm[1].L, p->A64.as<double>(), p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(),
-                                p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s));
+        MFS_TRY(launch_gemm_f64(G2, p->A64.as<double>(), p->ws_l64a.as<double>(), p->d_col_lam.as<int64_t>(),
+                                p->ws_l64b.as<double>(), p->d_col_lam.as<int64_t>(), p->gpart64.as<double>(), s,
+                                false));
+        sl.part = p->gpart64.ptr;
     }
     const void *lam = f32 ? (const void *)p->ws_l32b.ptr : (const void *)p->ws_l64b.ptr;
     void *S = nullptr, *L = nullptr;
@@ -1416,7 +1435,7 @@ int precond_fwd(mfs_plan p, const double *in, int prec, bool project, double *ou
         S = src_prec == MFS_MIXED ? p->fS32.ptr : p->fS64.ptr;
         L = src_prec == MFS_MIXED ? p->fL32.ptr : p->fL64.ptr;
     }
-    return launch_project(bv, lam, f32, true, project, out64, S, L, src_prec < 0 ? 0 : src_prec, s);
+    return launch_project(bv, lam, f32, true, project, out64, S, L, src_prec < 0 ? 0 : src_prec, s, &sl);
 }
 
 // out (gamma layout) = R (S_L^+)^T R^T [(I - L)] in   (in: lambda layout, world)

@@ -204,10 +204,14 @@ struct GemmLaunch {
     int vec4 = 0;  // every A row start and B column start is 16-byte aligned (float4 / double2 loads)
 };
 
+// sum_slices = false leaves a split GEMM's slices in `partial` (C is not written): the
+// consumer adds them (SplitSlices).
 int launch_gemm_f32(const GemmLaunch &G, const float *Apool, const float *B, const int64_t *b_col_off, float *C,
-                    const int64_t *c_col_off, float *partial, hipStream_t s);
+                    const int64_t *c_col_off, float *partial, hipStream_t s,
+                    bool sum_slices = true);
 int launch_gemm_f64(const GemmLaunch &G, const double *Apool, const double *B, const int64_t *b_col_off, double *C,
-                    const int64_t *c_col_off, double *partial, hipStream_t s);
+                    const int64_t *c_col_off, double *partial, hipStream_t s,
+                    bool sum_slices = true);
 
 // Per-body view used by rotation / projection / extraction kernels.
 struct BodyView {
@@ -237,8 +241,17 @@ int launch_cast(int64_t n, const void *in, bool in_f32, void *out, hipStream_t s
 // lam (lambda layout) -> optionally rotated to the world frame, optionally (I - L); written to out64
 // (may alias lam when lam is fp64 and rotate is false) and/or into the pair-sum source records
 // srcS / srcL (chosen by body kind; either may be null) of precision src_prec
+// Split-K slices of a GEMM whose columns are bodies, read in place of its output:
+// value j of body b = sum over sp < n of part[sp * split_stride + col_of_body[b] * col_stride + j],
+// added in slice order as the GEMM's own reduction does.
+struct SplitSlices {
+    const void *part = nullptr;
+    int n = 1;
+    int64_t split_stride = 0, col_stride = 0;
+    const int32_t *col_of_body = nullptr;
+};
 int launch_project(const BodyView &bv, const void *lam, bool lam_f32, bool rotate, bool project, double *out64,
-                   void *srcS, void *srcL, int src_prec, hipStream_t s);
+                   void *srcS, void *srcL, int src_prec, hipStream_t s, const SplitSlices *slices = nullptr);
 int launch_completion(const BodyView &bv, const double *net, double *s0, void *srcS, void *srcL, int src_prec,
                       hipStream_t s);
 int launch_extract(const BodyView &bv, const double *lam, const double *s0, double *out, double *sigma,
