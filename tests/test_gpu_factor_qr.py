@@ -110,13 +110,16 @@ def test_rank_deficient_block_is_refused(fact):
 
 
 @pytest.mark.timeout(600)
-def test_type_t_cluster_both_factorizations():
+def test_type_t_cluster_both_factorizations(capsys):
     """20 Type T ellipsoids built like the 10^4 case (N = 658, M = 842: blocks of
-    2526 x 1974): solves of SVD and QR plans against the oracle."""
+    2526 x 1974): solves of SVD and QR plans against the oracle.  Minutes of
+    oracle work on the host: each step reports as it ends, past output capture."""
     mfs = _mfs()
     wl = W.type_t_cluster(20, W.STOKES, 164)
     pr = O.Problem.from_workload(wl)
     sol = pr.solve(wl.net[0], tol=1e-12)
+    with capsys.disabled():
+        print(f"\ntype T: oracle solve done ({sol['iters']} iterations)", flush=True)
     ref = sol["out"]
     net = _dev(net_flat(wl))
     for fact in (mfs.FACTOR_SVD, mfs.FACTOR_QR):
@@ -130,8 +133,9 @@ def test_type_t_cluster_both_factorizations():
             e = rel_inf(out.cpu().numpy(), ref)
             bars = M.solve_bars(pr, wl.net[0], tol, sol, cap=1e-5, qr=fact == mfs.FACTOR_QR, dt=dt,
                                 gamma=info["gamma"].cpu().numpy())
-            print("type T", "QR" if fact else "SVD", prec, "iters", info["iters"], "err", e, bars,
-                  "ratio", plan.min_sigma_ratio, f"plan creation {t_setup:.3f} s", flush=True)
+            with capsys.disabled():
+                print("type T", "QR" if fact else "SVD", prec, "iters", info["iters"], "err", e, bars,
+                      "ratio", plan.min_sigma_ratio, f"plan creation {t_setup:.3f} s", flush=True)
             assert info["status"] == mfs.MFS_OK and bars["residual"] <= bars["residual_bound"] and e <= bars["out"]
             plan.close()
 
@@ -158,10 +162,11 @@ def test_qr_resistance_plan(kind):
 @pytest.mark.parametrize("kind,n_src,n_trg", [(W.LAPLACE, 10, 30), (W.STOKES, 10, 10), (W.STOKES, 11, 40),
                                               (W.LAPLACE, 64, 64)])
 def test_qr_small_square_and_ragged_blocks(kind, n_src, n_trg):
-    """Blocks narrower than one 32-column panel (10 or 30 columns), square
-    blocks (M = N: S_L^+ is the inverse), and a width one column past whole
-    panels (33 = 32 + 1): pseudo-inverse apply and matvec of QR plans against
-    the oracle, within 4 x the model of a QR plan of the same precision."""
+    """Blocks narrower than one 16-column panel (10 columns), a whole panel and a
+    ragged one (30 = 16 + 14), square blocks (M = N: S_L^+ is the inverse; 64 =
+    4 x 16 columns), and a width one column past whole panels (33 = 2 x 16 + 1):
+    pseudo-inverse apply and matvec of QR plans against the oracle, within 4 x
+    the model of a QR plan of the same precision."""
     mfs = _mfs()
     wl = W.small_cluster(3, kind, n_src, n_trg, seed=167, axes=(1.0, 1.0, 1.5))
     pr = O.Problem.from_workload(wl)
