@@ -643,7 +643,8 @@ def main():
                    "collocation_per_body": int(wl.shapes[0].trg.shape[0]),
                    "kernel": " + ".join(kind_name[k] for k in kinds) + (" + centre gradient" if grad else ""),
                    "gmres_tol": args.tol,
-                   "gmres_stop": f"estimate <= {STOP_FACTOR}*tol (mfs_plan_set_stop_factor), then FP64 true residual <= tol",
+                   "gmres_stop": (f"estimate <= {STOP_FACTOR}*tol (mfs_plan_set_stop_factor), then FP64 true residual "
+                                  f"<= {STOP_FACTOR}*tol by refinement (converged when <= tol)"),
                    "unknowns_gamma": plan_mx.n_gamma, "off_body_pairs_per_matvec": off_total,
                    "factorization": args.factorization},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

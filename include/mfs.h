@@ -299,12 +299,13 @@ int mfs_matvec_adjoint(mfs_plan plan, const double *w, double *out, int prec, vo
  * enqueues each iteration before it reads the status of the one before, so
  * the GPU does not wait for it (with a progress callback set it reads every
  * status first; the results are the same).
- * Every system stops on its own when ||r||_2 <= tol ||b||_2 (the iteration
- * aims at stop_factor * tol, a margin for the outputs' error; see
- * mfs_plan_set_stop_factor).  With a MIXED
- * plan the Krylov matvec is the mixed one; each attempt ends with an FP64
- * true-residual matvec, and systems above tol restart from their iterate on
- * that residual (iterative refinement, at most max_refine restarts).
+ * Every system stops on its own when ||r||_2 <= stop_factor tol ||b||_2 (a
+ * margin below tol for the outputs' error; see mfs_plan_set_stop_factor).  With
+ * a MIXED plan the Krylov matvec is the mixed one; each attempt ends with an
+ * FP64 true-residual matvec, and systems whose true residual is above
+ * stop_factor tol ||b||_2 restart from their iterate on that residual, each
+ * restart reducing it by stop_factor (iterative refinement, at most max_refine
+ * restarts).
  * iters [host][n_sys] receives the matvecs spent per system (mixed and FP64),
  * relres [host][n_sys] the final relative residual (the true FP64 one for
  * MIXED plans, the GMRES estimate for FP64 plans); either may be NULL.
@@ -394,8 +395,9 @@ int mfs_plan_last_solve(mfs_plan plan, int32_t *mixed_matvecs, int32_t *fp64_mat
  * grid).  Synchronous. */
 int mfs_plan_set_graph(mfs_plan plan, int32_t enable);
 /* Stopping margin of mfs_gmres_solve (and of the adjoint solve of
- * mfs_gmres_solve_backward): GMRES iterates until its residual estimate is at
- * most factor * tol * ||b||_2 per system (Section 4: GMRES with a relative
+ * mfs_gmres_solve_backward): GMRES iterates until its residual (the estimate;
+ * in MIXED plans then also the FP64 true residual, by refinement) is at most
+ * factor * tol * ||b||_2 per system (Section 4: GMRES with a relative
  * tolerance; factor 1 is that rule as stated), and a solve succeeds when the
  * final relative residual (the FP64 true one for MIXED plans) is at most tol.
  * The relative residual bounds the outputs' error only up to the conditioning
